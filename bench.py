@@ -1,0 +1,265 @@
+"""Throughput of the fused radiative-transfer LB stream-collide step on one MI355X.
+
+A step is one fused stream-and-collide pass (trilinear pull with inflow and
+vacuum faces, per-cell moments, implicit collision, store of the new
+populations, E and F, and the FP64 boundary/energy diagnostics) over the
+crossing-beams-plus-shadow workload: 256^3 cells, the 110-direction
+degree-17 Lebedev rule, FP32 population storage.  The same workload is
+then timed with BF16 and FP16 population storage.
+
+Prints ONE JSON line.  `value` is cell-direction updates per second (GDUPS)
+of the FP32 form with all inputs resident in HBM.  The roofline entry is
+for the fused step kernel: algorithmic bytes per launch over the kernel's
+mean duration, timed with HIP events on the stream the kernel runs on.
+The CPU baseline is the FP64 oracle (test infrastructure) timed on a bounded
+sample of the same workload on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "cell-direction updates/s (GDUPS) and % HBM peak, FP32 vs BF16-storage"
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2007_05718_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(f.encode())
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes_per_cell(ndir: int, pop_bytes: int, moment_bytes: int = 4) -> float:
+    """One read and one write of every population, the three coefficient
+    fields (kappa_a, kappa_s, eta: 12 B) and the E, F outputs (4 values)."""
+    return ndir * 2 * pop_bytes + 12 + 4 * moment_bytes
+
+
+def time_form(L, torch, prob, storage, steps, warmup, with_outputs=True):
+    """Returns (mean ms per step over the timed region, mean kernel ms)."""
+    desc = L.Desc.from_problem(prob, storage=storage)
+    ctx = L.lbrt_init(desc)
+    n = prob.ndir * prob.ncell
+    dt = {L.LBRT_FP32: torch.float32, L.LBRT_BF16: torch.bfloat16,
+          L.LBRT_FP16: torch.float16, L.LBRT_FP64: torch.float64}[storage]
+    Ia = torch.zeros(n, dtype=dt, device="cuda")
+    Ib = torch.zeros(n, dtype=dt, device="cuda")
+    f = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).reshape(-1).cuda()
+    ka, ks, eta = f(prob.kappa_a), f(prob.kappa_s), f(prob.eta)
+    inflow = [(p.face, p.direction, f(p.values)) for p in prob.inflow]
+    mdt = torch.float64 if storage == L.LBRT_FP64 else torch.float32
+    E = torch.empty(prob.ncell, dtype=mdt, device="cuda") if with_outputs else None
+    F = torch.empty(3 * prob.ncell, dtype=mdt, device="cuda") if with_outputs else None
+    diag = torch.zeros(L.LBRT_DIAG_LEN, dtype=torch.float64, device="cuda") if with_outputs else None
+    bufs = [Ia, Ib]
+    stream = torch.cuda.current_stream()
+
+    def one(k, events=None):
+        a, b = bufs[k % 2], bufs[(k + 1) % 2]
+        if events is not None:
+            events[0].record(stream)
+        L.lbrt_step(ctx, a, b, ka, ks, eta, inflow=inflow or None, nsteps=1, E=E, F=F,
+                    diag=diag, stream=stream.cuda_stream)
+        if events is not None:
+            events[1].record(stream)
+
+    for k in range(warmup):
+        one(k)
+    torch.cuda.synchronize()
+    # Per-launch kernel time: events bracket each lbrt_step call.  With
+    # outputs on, a call is the step kernel plus the tiny diagnostics
+    # reduction; kernel-only time comes from a second pass without outputs.
+    t0 = time.perf_counter()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    for k in range(steps):
+        one(warmup + k, evs[k])
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    per_call = [a.elapsed_time(b) for a, b in evs]
+    del Ia, Ib
+    ctx.close()
+    return wall, float(np.mean(per_call)), float(np.min(per_call))
+
+
+def kernel_only_ms(L, torch, prob, storage, steps):
+    """Mean duration of the step kernel alone (E, F written, no diagnostics)."""
+    desc = L.Desc.from_problem(prob, storage=storage)
+    ctx = L.lbrt_init(desc)
+    n = prob.ndir * prob.ncell
+    dt = {L.LBRT_FP32: torch.float32, L.LBRT_BF16: torch.bfloat16,
+          L.LBRT_FP16: torch.float16}[storage]
+    Ia = torch.zeros(n, dtype=dt, device="cuda")
+    Ib = torch.zeros(n, dtype=dt, device="cuda")
+    f = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).reshape(-1).cuda()
+    ka, ks, eta = f(prob.kappa_a), f(prob.kappa_s), f(prob.eta)
+    inflow = [(p.face, p.direction, f(p.values)) for p in prob.inflow]
+    E = torch.empty(prob.ncell, dtype=torch.float32, device="cuda")
+    F = torch.empty(3 * prob.ncell, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    bufs = [Ia, Ib]
+    for k in range(3):
+        L.lbrt_step(ctx, bufs[k % 2], bufs[(k + 1) % 2], ka, ks, eta, inflow=inflow or None,
+                    E=E, F=F, stream=stream.cuda_stream)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    for k in range(steps):
+        evs[k][0].record(stream)
+        L.lbrt_step(ctx, bufs[k % 2], bufs[(k + 1) % 2], ka, ks, eta, inflow=inflow or None,
+                    E=E, F=F, stream=stream.cuda_stream)
+        evs[k][1].record(stream)
+    torch.cuda.synchronize()
+    ms = [a.elapsed_time(b) for a, b in evs]
+    ctx.close()
+    return float(np.mean(ms))
+
+
+def cpu_baseline(prob, planes: int = 16):
+    """FP64 oracle, one step on a slab of `planes` z-planes of the workload."""
+    import copy
+
+    import workloads as wl
+    from oracle import lbrt_oracle as orc
+    q = copy.copy(prob)
+    q.nz = planes
+    q.kappa_a = prob.kappa_a[:planes]
+    q.kappa_s = prob.kappa_s[:planes]
+    q.eta = prob.eta[:planes]
+    q.inflow = [wl.InflowPlane(p.face, p.direction,
+                               p.values[:planes] if p.face in (0, 1, 2, 3) else p.values)
+                for p in prob.inflow]
+    rng = np.random.default_rng(0)
+    I = rng.uniform(0.0, 1.0, (q.ndir, planes, q.ny, q.nx)) * q.weights[:, None, None, None]
+    t0 = time.perf_counter()
+    orc.step(I, q)
+    sec = time.perf_counter() - t0
+    updates = q.ndir * q.ncell
+    return {"value": updates / sec / 1e9, "unit": "GDUPS", "cores": 1, "kind": "oracle",
+            "sample": f"one FP64 step on a {q.nx}x{q.ny}x{planes} slab of the workload "
+                      f"({q.ndir} directions, {updates:.3g} updates, {sec:.1f} s, numpy, "
+                      f"single thread)"}
+
+
+def traffic_entry(ndir, ncell):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "step_kernel_beams256_fp32_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("kernel_source_digest") != kernel_source_digest():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=256, help="grid edge (default 256)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--forms", default="bf16,fp16", help="extra storage forms to time")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU slab decomposition is a design, not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2007_05718_amd as L
+    import workloads as wl
+
+    log("generating workload")
+    prob = wl.beams(n=args.n, alloc_state=False)
+    ndir, ncell = prob.ndir, prob.ncell
+    updates = ndir * ncell
+
+    log("timing fp32")
+    wall, call_ms, call_min = time_form(L, torch, prob, L.LBRT_FP32, args.steps, args.warmup)
+    log("timing fp32 kernel alone")
+    kms = kernel_only_ms(L, torch, prob, L.LBRT_FP32, args.steps)
+    gdups = updates / (wall * 1e-3) / 1e9
+    bpc = algorithmic_bytes_per_cell(ndir, 4)
+    bytes_launch = bpc * ncell
+    achieved = bytes_launch / (kms * 1e-3) / 1e9
+    forms = {}
+    for name in [s for s in args.forms.split(",") if s]:
+        st = {"bf16": L.LBRT_BF16, "fp16": L.LBRT_FP16}[name]
+        log(f"timing {name}")
+        w2, c2, _ = time_form(L, torch, prob, st, args.steps, args.warmup)
+        k2 = kernel_only_ms(L, torch, prob, st, args.steps)
+        b2 = algorithmic_bytes_per_cell(ndir, 2) * ncell
+        forms[name] = {
+            "GDUPS": round(updates / (w2 * 1e-3) / 1e9, 2),
+            "ms_per_step": round(w2, 4),
+            "kernel_ms": round(k2, 4),
+            "hbm_GBs_algorithmic": round(b2 / (k2 * 1e-3) / 1e9, 1),
+            "speedup_vs_fp32": round(wall / w2, 3),
+        }
+    cpu = None
+    if not args.no_cpu:
+        log("timing the oracle on the host")
+        cpu = cpu_baseline(prob)
+    tr = traffic_entry(ndir, ncell)
+    out = {
+        "metric": METRIC,
+        "value": round(gdups, 2),
+        "unit": "GDUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"crossing beams + opaque sphere, {args.n}^3 cells x {ndir}-direction "
+                        "Lebedev (degree 17), FP32 population storage, implicit collision, "
+                        "dt=0.5 dx, inflow (-x,-y) and vacuum faces, E/F and FP64 "
+                        "diagnostics every step",
+            "cells": ncell, "directions": ndir, "updates_per_step": updates,
+            "hbm_pct_algorithmic": round(100.0 * gdups * bpc / ndir / HBM_PEAK_GBS, 2),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": tr,
+            "kernel": "step_kernel<float,110>",
+            "kernel_ms": round(kms, 4),
+            "bytes_per_launch_algorithmic": bytes_launch,
+        },
+        "cpu_baseline": cpu,
+        "forms": forms,
+        "kernel_source_digest": kernel_source_digest(),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,179 @@
+/*
+ * lbrt — fused stream-and-collide step of the grey radiative-transfer
+ * lattice-Boltzmann scheme of Weih, Gabbana, Simeoni, Rezzolla, Succi and
+ * Tripiccione (2020), for AMD MI355X (gfx950).
+ *
+ * One step (Sec. 3.3 "Numerical procedure") does, for every cell r and
+ * discrete direction n_i:
+ *   stream   I*_i(r) = I_i(r - n_i dt), by the trilinear interpolation of
+ *            eq. (interp) from the 2x2x2 upwind cells;
+ *   moments  E* = sum_i I*_i, F* = sum_i n_i I*_i (eq. moments_discrete);
+ *   collide  relax toward the isotropic equilibrium w_i (E + lambda n_i.F)
+ *            with absorption kappa_a, emission eta and scattering kappa_s
+ *            (eqs. rte_gray_bgkform, source-and-equil), implicitly
+ *            (eq. rte_implicit), explicitly (eq. collision-step) or by a
+ *            fixed number of Lambda-iteration cycles; or, for a moving
+ *            fluid, the implicit mixed-frame equation of App. B.
+ *
+ * Conventions shared by every entry point
+ *   - Uniform Cartesian grid nx * ny * nz, spacing dx; cell (x, y, z) has
+ *     linear index x + nx * (y + ny * z).
+ *   - Populations are weight-absorbed, I_i = w_i I(n_i) (Sec. 3.2), stored
+ *     structure-of-arrays, direction-major: element (i, cell) at
+ *     i * ncell + cell, in the context's storage type.  BF16 and FP16
+ *     storage hold I_i / s_i with a per-direction scale s_i (default |w_i|).
+ *   - Per-cell coefficient fields are float32 arrays of ncell values.
+ *     kappa_s is the isotropic scattering coefficient kappa_0 of
+ *     eq. (rte_gray); lambda = 3 kappa_1 / kappa_0 is a scalar of the context.
+ *     With a moving fluid, kappa_a, kappa_s and eta are fluid-frame values and
+ *     vel holds (vx[ncell], vy[ncell], vz[ncell]) in units of c.
+ *   - Device pointers are plain HIP device addresses owned by the caller;
+ *     the library never frees them.  Work is enqueued on the caller's HIP
+ *     stream (a hipStream_t passed as void*, NULL = default stream) and is
+ *     asynchronous; errors detected on the host are returned before any
+ *     launch.  Every call returns an lbrt_status code and never aborts;
+ *     lbrt_last_error() gives a message for the calling thread.
+ */
+#ifndef LBRT_H
+#define LBRT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbrt_ctx lbrt_ctx;
+
+typedef enum {
+  LBRT_OK = 0,
+  LBRT_E_INVAL = -1,        /* bad argument: null pointer, bad size or enum     */
+  LBRT_E_CFL = -2,          /* dt > dx: the 2x2x2 stencil spans one cell only   */
+  LBRT_E_QUAD = -3,         /* directions/weights violate the rule identities   */
+  LBRT_E_NOMEM = -4,        /* device allocation for the context tables failed  */
+  LBRT_E_HIP = -5,          /* a HIP runtime call failed                        */
+  LBRT_E_UNSUPPORTED = -6   /* valid but not supported combination              */
+} lbrt_status;
+
+typedef enum { LBRT_BC_OUTFLOW = 0, LBRT_BC_PERIODIC = 1, LBRT_BC_INFLOW = 2 } lbrt_bc;
+typedef enum { LBRT_FP32 = 0, LBRT_FP64 = 1, LBRT_BF16 = 2, LBRT_FP16 = 3 } lbrt_storage;
+typedef enum {
+  LBRT_COLL_IMPLICIT = 0,   /* eq. (rte_implicit), solved exactly                */
+  LBRT_COLL_EXPLICIT = 1,   /* eq. (collision-step)                              */
+  LBRT_COLL_LAMBDA = 2      /* Lambda iteration, lambda_iters cycles (Sec. 3.3)  */
+} lbrt_collision;
+
+enum { LBRT_MAX_DIRS = 160, LBRT_MAX_INFLOW = 32, LBRT_DIAG_LEN = 9 };
+
+/* Face order used by bc[], inflow planes and diagnostics. */
+enum { LBRT_FACE_MX = 0, LBRT_FACE_PX = 1, LBRT_FACE_MY = 2, LBRT_FACE_PY = 3,
+       LBRT_FACE_MZ = 4, LBRT_FACE_PZ = 5 };
+
+/*
+ * Problem statement (Sec. 3.2-3.3; boundaries Sec. 4.1.1 and 4.2.1).
+ *   dirs     host, ndir x 3 unit vectors n_i (row i = (nx, ny, nz));
+ *   weights  host, ndir nonzero quadrature weights, sum 1 (Sec. 3.2.1; some
+ *            Lebedev rules carry negative weights);
+ *   scale    host, ndir per-direction storage scales s_i > 0 for BF16/FP16,
+ *            or NULL for s_i = |w_i|; ignored for FP32/FP64;
+ *   bc       per face: outflow (vacuum ghosts, nothing enters), periodic
+ *            (both faces of an axis), or inflow (ghost values given per step
+ *            as lbrt_inflow planes; ghosts not given are vacuum);
+ *   lambda_iters  cycles for LBRT_COLL_LAMBDA (>= 1);
+ *   lambda_aniso  lambda = 3 kappa_1 / kappa_0 (0 for isotropic scattering);
+ *   moving_fluid  nonzero: lbrt_step takes a velocity field and uses the
+ *            mixed-frame collision of App. B (implicit, lambda must be 0).
+ * The context copies everything it needs; the caller's arrays may be freed
+ * after lbrt_init returns.
+ */
+typedef struct {
+  int32_t nx, ny, nz;
+  double dx, dt;
+  int32_t ndir;
+  const double *dirs;
+  const double *weights;
+  const double *scale;
+  int32_t bc[6];
+  int32_t storage;
+  int32_t collision;
+  int32_t lambda_iters;
+  double lambda_aniso;
+  int32_t moving_fluid;
+} lbrt_desc;
+
+/*
+ * Prescribed ghost values for direction `dir` on inflow face `face`
+ * (the beam injection of Sec. 4.1.1).  `values` is a device float32 array
+ * in the face's own layout: x faces [z][y], y faces [z][x], z faces [y][x].
+ * It is read when a population streams in through that face: only
+ * directions that enter through the face may be listed.
+ */
+typedef struct {
+  int32_t face;
+  int32_t dir;
+  const float *values;
+} lbrt_inflow;
+
+/* Host-only check of a problem statement; needs no GPU.  Rejects
+ * dt <= 0 or dt > dx (LBRT_E_CFL), dims < 2, ndir outside [2, LBRT_MAX_DIRS],
+ * non-unit directions, |sum w - 1|, |sum w n|, |sum w n n - I/3| > 1e-12
+ * (LBRT_E_QUAD: the collision relies on these identities, App. A.1
+ * eq. stencil-symmetry), a periodic flag on one face of an axis only,
+ * bad enums, negative scales, lambda_iters < 1 in Lambda mode, and
+ * moving_fluid with lambda != 0 or a non-implicit collision. */
+int lbrt_validate(const lbrt_desc *desc);
+
+/* Validate, then build a context on the current HIP device: direction and
+ * stencil tables in device memory, a small reduction buffer for the
+ * diagnostics, kernel selection.  *out is set only on success. */
+int lbrt_init(const lbrt_desc *desc, lbrt_ctx **out);
+
+/* Free the context's device tables.  NULL is accepted. */
+void lbrt_destroy(lbrt_ctx *ctx);
+
+/*
+ * nsteps >= 0 stream-collide steps.  Step k reads I_a (k even) or I_b
+ * (k odd) and writes the other buffer (ping-pong; in-place is rejected):
+ * the result is in I_b when nsteps is odd, in I_a otherwise.
+ *   kappa_a, kappa_s, eta  required (device float32, ncell each);
+ *   vel      device float32 3 x ncell, required iff moving_fluid;
+ *   inflow   host array of ninflow planes (ninflow <= LBRT_MAX_INFLOW), or
+ *            NULL/0; each plane must name an inflow face and a direction
+ *            entering through it;
+ *   E, F     device, or NULL: moments of the final state, E[ncell] and
+ *            F[3][ncell] (x, y, z components), float64 for FP64 storage and
+ *            float32 otherwise;
+ *   diag     device float64[LBRT_DIAG_LEN], or NULL:
+ *            [0] sum over cells of E after the last step,
+ *            [1..6] energy streamed out through faces -x,+x,-y,+y,-z,+z,
+ *                   summed over the call's steps (a point outside along
+ *                   several axes is booked on the first of x, y, z),
+ *            [7] energy streamed in from inflow ghosts, summed over steps,
+ *            [8] sum over cells of the streamed E* of the last step.
+ *            diag is overwritten by the call.
+ */
+int lbrt_step(lbrt_ctx *ctx, void *I_a, void *I_b,
+              const float *kappa_a, const float *kappa_s, const float *eta,
+              const float *vel, const lbrt_inflow *inflow, int32_t ninflow,
+              int32_t nsteps, void *E, void *F, double *diag, void *stream);
+
+/* Moments E = sum_i I_i and F = sum_i n_i I_i (eq. moments_discrete) of a
+ * stored state I; E, F as in lbrt_step (either may be NULL). */
+int lbrt_moments(lbrt_ctx *ctx, const void *I, void *E, void *F, void *stream);
+
+/* Convert a population array between storage types with the context's
+ * per-direction scales (e.g. to encode an initial state for BF16/FP16
+ * storage, or decode one for inspection).  src and dst must not overlap. */
+int lbrt_convert(lbrt_ctx *ctx, const void *src, int32_t src_storage,
+                 void *dst, int32_t dst_storage, void *stream);
+
+/* Message describing the last error returned on the calling thread
+ * (empty string if none).  The pointer stays valid until the thread's next
+ * lbrt call. */
+const char *lbrt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBRT_H */

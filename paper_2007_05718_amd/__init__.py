@@ -1,0 +1,273 @@
+"""lbrt: fused stream-and-collide step of the grey radiative-transfer
+lattice-Boltzmann scheme (Weih et al. 2020) on AMD MI355X.
+
+This module is a thin ctypes binding over the C ABI in ``include/lbrt.h``:
+the functions below carry the same names as the C entry points and only
+marshal arguments (torch tensors -> device pointers, the current torch
+stream -> hipStream_t).  Every step of the computation runs in the HIP
+kernels of ``_lib/liblbrt.so``; there is no Python or CPU fallback, and
+importing this module fails loudly when the library has not been built
+(``python -m paper_2007_05718_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "liblbrt.so")
+
+LBRT_OK, LBRT_E_INVAL, LBRT_E_CFL, LBRT_E_QUAD = 0, -1, -2, -3
+LBRT_E_NOMEM, LBRT_E_HIP, LBRT_E_UNSUPPORTED = -4, -5, -6
+LBRT_BC_OUTFLOW, LBRT_BC_PERIODIC, LBRT_BC_INFLOW = 0, 1, 2
+LBRT_FP32, LBRT_FP64, LBRT_BF16, LBRT_FP16 = 0, 1, 2, 3
+LBRT_COLL_IMPLICIT, LBRT_COLL_EXPLICIT, LBRT_COLL_LAMBDA = 0, 1, 2
+LBRT_MAX_DIRS, LBRT_MAX_INFLOW, LBRT_DIAG_LEN = 160, 32, 9
+
+STORAGE_BYTES = {LBRT_FP32: 4, LBRT_FP64: 8, LBRT_BF16: 2, LBRT_FP16: 2}
+STORAGE_NAMES = {LBRT_FP32: "fp32", LBRT_FP64: "fp64", LBRT_BF16: "bf16", LBRT_FP16: "fp16"}
+
+
+class lbrt_desc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("dx", ctypes.c_double), ("dt", ctypes.c_double),
+        ("ndir", ctypes.c_int32),
+        ("dirs", ctypes.POINTER(ctypes.c_double)),
+        ("weights", ctypes.POINTER(ctypes.c_double)),
+        ("scale", ctypes.POINTER(ctypes.c_double)),
+        ("bc", ctypes.c_int32 * 6),
+        ("storage", ctypes.c_int32),
+        ("collision", ctypes.c_int32),
+        ("lambda_iters", ctypes.c_int32),
+        ("lambda_aniso", ctypes.c_double),
+        ("moving_fluid", ctypes.c_int32),
+    ]
+
+
+class lbrt_inflow(ctypes.Structure):
+    _fields_ = [("face", ctypes.c_int32), ("dir", ctypes.c_int32),
+                ("values", ctypes.c_void_p)]
+
+
+class LbrtError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lbrt error {code}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"lbrt HIP library missing at {LIB_PATH}; build it with "
+                          "`python -m paper_2007_05718_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)
+    lib.lbrt_validate.argtypes = [ctypes.POINTER(lbrt_desc)]
+    lib.lbrt_validate.restype = ctypes.c_int
+    lib.lbrt_init.argtypes = [ctypes.POINTER(lbrt_desc), ctypes.POINTER(vp)]
+    lib.lbrt_init.restype = ctypes.c_int
+    lib.lbrt_destroy.argtypes = [vp]
+    lib.lbrt_destroy.restype = None
+    lib.lbrt_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(lbrt_inflow), i32,
+                              i32, vp, vp, vp, vp]
+    lib.lbrt_step.restype = ctypes.c_int
+    lib.lbrt_moments.argtypes = [vp, vp, vp, vp, vp]
+    lib.lbrt_moments.restype = ctypes.c_int
+    lib.lbrt_convert.argtypes = [vp, vp, i32, vp, i32, vp]
+    lib.lbrt_convert.restype = ctypes.c_int
+    lib.lbrt_last_error.argtypes = []
+    lib.lbrt_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = _load()
+
+
+def lbrt_last_error() -> str:
+    return (_lib.lbrt_last_error() or b"").decode()
+
+
+def _check(rc: int) -> None:
+    if rc != LBRT_OK:
+        raise LbrtError(rc, lbrt_last_error())
+
+
+class Desc:
+    """An ``lbrt_desc`` plus the host arrays it points to."""
+
+    def __init__(self, nx: int, ny: int, nz: int, dt: float, dirs, weights,
+                 bc: Sequence[int] = (LBRT_BC_OUTFLOW,) * 6, dx: float = 1.0,
+                 storage: int = LBRT_FP32, collision: int = LBRT_COLL_IMPLICIT,
+                 lambda_iters: int = 5, lam: float = 0.0, moving_fluid: bool = False,
+                 scale=None):
+        self.dirs = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
+        self.weights = np.ascontiguousarray(weights, dtype=np.float64).reshape(-1)
+        self.scale = None if scale is None else np.ascontiguousarray(scale, dtype=np.float64)
+        d = lbrt_desc()
+        d.nx, d.ny, d.nz = int(nx), int(ny), int(nz)
+        d.dx, d.dt = float(dx), float(dt)
+        d.ndir = int(self.weights.shape[0])
+        dptr = ctypes.POINTER(ctypes.c_double)
+        d.dirs = self.dirs.ctypes.data_as(dptr)
+        d.weights = self.weights.ctypes.data_as(dptr)
+        d.scale = self.scale.ctypes.data_as(dptr) if self.scale is not None else None
+        for f in range(6):
+            d.bc[f] = int(bc[f])
+        d.storage = int(storage)
+        d.collision = int(collision)
+        d.lambda_iters = int(lambda_iters)
+        d.lambda_aniso = float(lam)
+        d.moving_fluid = 1 if moving_fluid else 0
+        self.c = d
+
+    @property
+    def ncell(self) -> int:
+        return self.c.nx * self.c.ny * self.c.nz
+
+    @property
+    def ndir(self) -> int:
+        return self.c.ndir
+
+    @classmethod
+    def from_problem(cls, prob, storage: int = LBRT_FP32, **kw) -> "Desc":
+        args = dict(nx=prob.nx, ny=prob.ny, nz=prob.nz, dt=prob.dt, dirs=prob.dirs,
+                    weights=prob.weights, bc=prob.bc, dx=prob.dx, storage=storage,
+                    collision=prob.collision, lambda_iters=prob.lambda_iters, lam=prob.lam,
+                    moving_fluid=prob.vel is not None)
+        args.update(kw)
+        return cls(**args)
+
+
+def lbrt_validate(desc: Desc) -> int:
+    """Host-only validation; returns the lbrt status code."""
+    return int(_lib.lbrt_validate(ctypes.byref(desc.c)))
+
+
+class Context:
+    """Owns an ``lbrt_ctx``; destroyed with ``lbrt_destroy`` when collected."""
+
+    def __init__(self, handle: int, desc: Desc):
+        self.handle = ctypes.c_void_p(handle)
+        self.desc = desc
+
+    def close(self):
+        if self.handle:
+            _lib.lbrt_destroy(self.handle)
+            self.handle = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lbrt_init(desc: Desc) -> Context:
+    h = ctypes.c_void_p()
+    _check(_lib.lbrt_init(ctypes.byref(desc.c), ctypes.byref(h)))
+    return Context(h.value, desc)
+
+
+def lbrt_destroy(ctx: Context) -> None:
+    ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# torch marshalling
+# ---------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t, what: str, numel: Optional[int] = None, dtype=None):
+    if t is None:
+        return None
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what}: expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{what}: tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: tensor must be contiguous")
+    if dtype is not None and t.dtype not in (dtype if isinstance(dtype, tuple) else (dtype,)):
+        raise ValueError(f"{what}: dtype {t.dtype} not accepted")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{what}: {t.numel()} elements, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _pop_dtype(storage: int):
+    torch = _torch()
+    return {LBRT_FP32: torch.float32, LBRT_FP64: torch.float64,
+            LBRT_BF16: (torch.bfloat16, torch.int16, torch.uint16),
+            LBRT_FP16: (torch.float16, torch.int16, torch.uint16)}[storage]
+
+
+def _moment_dtype(storage: int):
+    torch = _torch()
+    return torch.float64 if storage == LBRT_FP64 else torch.float32
+
+
+def lbrt_step(ctx: Context, I_a, I_b, kappa_a, kappa_s, eta, vel=None, inflow=None,
+              nsteps: int = 1, E=None, F=None, diag=None, stream=None) -> None:
+    """``nsteps`` steps, ping-pong between I_a and I_b (result in I_b when
+    nsteps is odd).  ``inflow`` is a list of (face, dir, values_tensor)."""
+    d = ctx.desc
+    n, nc = d.ndir, d.ncell
+    st = d.c.storage
+    planes = None
+    nin = 0
+    if inflow:
+        nin = len(inflow)
+        planes = (lbrt_inflow * nin)()
+        for j, (face, direction, vals) in enumerate(inflow):
+            planes[j].face = int(face)
+            planes[j].dir = int(direction)
+            planes[j].values = _ptr(vals, f"inflow[{j}]", dtype=_torch().float32).value
+    f32 = _torch().float32
+    rc = _lib.lbrt_step(
+        ctx.handle, _ptr(I_a, "I_a", n * nc, _pop_dtype(st)),
+        _ptr(I_b, "I_b", n * nc, _pop_dtype(st)),
+        _ptr(kappa_a, "kappa_a", nc, f32), _ptr(kappa_s, "kappa_s", nc, f32),
+        _ptr(eta, "eta", nc, f32), _ptr(vel, "vel", 3 * nc, f32), planes, nin, int(nsteps),
+        _ptr(E, "E", nc, _moment_dtype(st)), _ptr(F, "F", 3 * nc, _moment_dtype(st)),
+        _ptr(diag, "diag", LBRT_DIAG_LEN, _torch().float64), _stream(stream))
+    _check(rc)
+
+
+def lbrt_moments(ctx: Context, I, E=None, F=None, stream=None) -> None:
+    d = ctx.desc
+    st = d.c.storage
+    _check(_lib.lbrt_moments(ctx.handle, _ptr(I, "I", d.ndir * d.ncell, _pop_dtype(st)),
+                             _ptr(E, "E", d.ncell, _moment_dtype(st)),
+                             _ptr(F, "F", 3 * d.ncell, _moment_dtype(st)), _stream(stream)))
+
+
+def lbrt_convert(ctx: Context, src, src_storage: int, dst, dst_storage: int,
+                 stream=None) -> None:
+    d = ctx.desc
+    n = d.ndir * d.ncell
+    _check(_lib.lbrt_convert(ctx.handle, _ptr(src, "src", n, _pop_dtype(src_storage)),
+                             int(src_storage), _ptr(dst, "dst", n, _pop_dtype(dst_storage)),
+                             int(dst_storage), _stream(stream)))
+
+
+def exported_symbols() -> list:
+    """Names of the C entry points the binding wraps."""
+    return ["lbrt_validate", "lbrt_init", "lbrt_destroy", "lbrt_step", "lbrt_moments",
+            "lbrt_convert", "lbrt_last_error"]
+
+
+def library():
+    return _lib

@@ -1,0 +1,462 @@
+// Host side of the C ABI: validation, context tables, kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbrt_internal.h"
+
+namespace lbrt {
+StepLauncher step_launcher_f32(int);
+StepLauncher step_launcher_f64(int);
+StepLauncher step_launcher_bf16(int);
+StepLauncher step_launcher_f16(int);
+
+StepLauncher step_launcher(int storage, int bucket_index) {
+  switch (storage) {
+    case LBRT_FP32: return step_launcher_f32(bucket_index);
+    case LBRT_FP64: return step_launcher_f64(bucket_index);
+    case LBRT_BF16: return step_launcher_bf16(bucket_index);
+    case LBRT_FP16: return step_launcher_f16(bucket_index);
+    default: return nullptr;
+  }
+}
+}  // namespace lbrt
+
+using namespace lbrt;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  return fail(LBRT_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t storage_bytes(int s) {
+  switch (s) {
+    case LBRT_FP32: return 4;
+    case LBRT_FP64: return 8;
+    default: return 2;
+  }
+}
+
+struct TileShape { int tx, ty, tz; };
+
+}  // namespace
+
+struct lbrt_ctx {
+  lbrt_desc desc;                 // pointers in desc are not kept
+  std::vector<double> dirs, weights, scales;
+  int bucket = 0;                 // index into kBuckets
+  int nb = 0;                     // bucket size
+  bool paired = false;
+  std::vector<int> order;         // processing index -> storage plane
+  void *tab_dev = nullptr;        // DirTab<float> or DirTab<double>, nb entries
+  void *tab_moments_dev = nullptr;
+  double *scales_dev = nullptr;   // per storage plane
+  double *partials = nullptr;     // per-block diagnostics
+  int partials_cap = 0;
+  TileShape tile{64, 4, 1};
+  int device = 0;
+};
+
+namespace {
+
+bool is_periodic_pair_ok(const int32_t *bc) {
+  for (int a = 0; a < 3; ++a) {
+    const bool lo = bc[2 * a] == LBRT_BC_PERIODIC, hi = bc[2 * a + 1] == LBRT_BC_PERIODIC;
+    if (lo != hi) return false;
+  }
+  return true;
+}
+
+int bucket_for(int ndir) {
+  for (int b = 0; b < kNumBuckets; ++b)
+    if (kBuckets[b] >= ndir) return b;
+  return -1;
+}
+
+TileShape default_tile(int nx, int ny, int nz) {
+  if (const char *env = std::getenv("LBRT_TILE")) {
+    TileShape t{};
+    if (std::sscanf(env, "%dx%dx%d", &t.tx, &t.ty, &t.tz) == 3 && t.tx * t.ty * t.tz == kBlock)
+      return t;
+  }
+  (void)ny;
+  (void)nz;
+  if (nx >= 64) return {64, 4, 1};
+  if (nx >= 32) return {32, 8, 1};
+  return {16, 16, 1};
+}
+
+template <typename T>
+void build_table(const lbrt_ctx &c, std::vector<DirTab<T>> &tab) {
+  const lbrt_desc &d = c.desc;
+  tab.assign(c.nb, DirTab<T>{});
+  const double dx = d.dx, dt = d.dt;
+  const int64_t sy = d.nx, sz = (int64_t)d.nx * d.ny;
+  for (int k = 0; k < c.nb; ++k) {
+    DirTab<T> &e = tab[k];
+    std::memset(&e, 0, sizeof(e));
+    if (k >= d.ndir) {  // null direction: loads its own cell of plane order[0], weight 0
+      e.plane = c.order[0];
+      e.scale = T(1);
+      e.inv_scale = T(1);
+      continue;
+    }
+    const int i = c.order[k];
+    const double *n = &c.dirs[3 * i];
+    double delta[3];
+    int s[3];
+    for (int a = 0; a < 3; ++a) {
+      delta[a] = dt * std::fabs(n[a]) / dx;
+      s[a] = n[a] > 0.0 ? 1 : (n[a] < 0.0 ? -1 : 0);
+      if (delta[a] == 0.0) s[a] = 0;
+    }
+    for (int b = 0; b < 8; ++b) {
+      const int bx = b & 1, by = (b >> 1) & 1, bz = b >> 2;
+      const double wx = bx ? delta[0] : 1.0 - delta[0];
+      const double wy = by ? delta[1] : 1.0 - delta[1];
+      const double wz = bz ? delta[2] : 1.0 - delta[2];
+      e.tw[b] = (T)(wx * wy * wz);
+      e.off[b] = (int32_t)(-(bx * s[0] + by * s[1] * sy + bz * s[2] * sz));
+    }
+    e.w = (T)c.weights[i];
+    for (int a = 0; a < 3; ++a) {
+      e.n[a] = (T)n[a];
+      e.delta[a] = (T)delta[a];
+      e.s[a] = s[a];
+    }
+    e.scale = (T)c.scales[i];
+    e.inv_scale = (T)(1.0 / c.scales[i]);
+    e.plane = i;
+  }
+}
+
+int ensure_partials(lbrt_ctx *c, int nblocks) {
+  if (nblocks <= c->partials_cap) return LBRT_OK;
+  if (c->partials) (void)hipFree(c->partials);
+  c->partials = nullptr;
+  c->partials_cap = 0;
+  hipError_t e = hipMalloc(&c->partials, sizeof(double) * kDiag * (size_t)nblocks);
+  if (e != hipSuccess) return fail(LBRT_E_NOMEM, "hipMalloc(diagnostic partials): %s",
+                                   hipGetErrorString(e));
+  c->partials_cap = nblocks;
+  return LBRT_OK;
+}
+
+KParams make_params(const lbrt_ctx *c) {
+  const lbrt_desc &d = c->desc;
+  KParams p{};
+  p.nx = d.nx;
+  p.ny = d.ny;
+  p.nz = d.nz;
+  p.ndir = d.ndir;
+  p.ncell = (int64_t)d.nx * d.ny * d.nz;
+  p.tx = c->tile.tx;
+  p.ty = c->tile.ty;
+  p.tz = c->tile.tz;
+  p.ntx = (d.nx + p.tx - 1) / p.tx;
+  p.nty = (d.ny + p.ty - 1) / p.ty;
+  p.ntz = (d.nz + p.tz - 1) / p.tz;
+  p.ntiles = p.ntx * p.nty * p.ntz;
+  for (int a = 0; a < 3; ++a) p.periodic[a] = d.bc[2 * a] == LBRT_BC_PERIODIC;
+  for (int f = 0; f < 6; ++f) p.inflow_face[f] = d.bc[f] == LBRT_BC_INFLOW;
+  p.mode = d.collision;
+  p.lambda_iters = d.lambda_iters;
+  p.flags = 0;
+  if (c->paired) p.flags |= KF_PAIRED;
+  if (d.moving_fluid) p.flags |= KF_MOVING;
+  if (d.lambda_aniso == 0.0) p.flags |= KF_LAMZERO;
+  p.dt = d.dt;  // time step in length units (c = 1)
+  p.lam = d.lambda_aniso;
+  return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lbrt_last_error(void) { return g_err.c_str(); }
+
+int lbrt_validate(const lbrt_desc *d) {
+  if (!d) return fail(LBRT_E_INVAL, "desc is NULL");
+  if (d->nx < 2 || d->ny < 2 || d->nz < 2)
+    return fail(LBRT_E_INVAL, "grid %d x %d x %d: every dimension must be >= 2", d->nx, d->ny,
+                d->nz);
+  const int64_t ncell = (int64_t)d->nx * d->ny * d->nz;
+  if (ncell >= (int64_t)1 << 31 || (int64_t)d->nx * d->ny >= (int64_t)1 << 30)
+    return fail(LBRT_E_INVAL, "grid too large: ncell must be < 2^31");
+  if (!(d->dx > 0.0) || !std::isfinite(d->dx)) return fail(LBRT_E_INVAL, "dx must be > 0");
+  if (!(d->dt > 0.0) || !std::isfinite(d->dt)) return fail(LBRT_E_CFL, "dt must be > 0");
+  if (d->dt > d->dx)
+    return fail(LBRT_E_CFL, "dt = %g > dx = %g: the trilinear pull spans one cell only",
+                d->dt, d->dx);
+  if (d->ndir < 2 || d->ndir > LBRT_MAX_DIRS)
+    return fail(LBRT_E_INVAL, "ndir = %d outside [2, %d]", d->ndir, (int)LBRT_MAX_DIRS);
+  if (!d->dirs || !d->weights) return fail(LBRT_E_INVAL, "dirs and weights are required");
+  for (int f = 0; f < 6; ++f)
+    if (d->bc[f] < LBRT_BC_OUTFLOW || d->bc[f] > LBRT_BC_INFLOW)
+      return fail(LBRT_E_INVAL, "bc[%d] = %d is not a boundary kind", f, d->bc[f]);
+  if (!is_periodic_pair_ok(d->bc))
+    return fail(LBRT_E_INVAL, "periodic boundaries must be set on both faces of an axis");
+  if (d->storage < LBRT_FP32 || d->storage > LBRT_FP16)
+    return fail(LBRT_E_INVAL, "storage = %d is not a storage type", d->storage);
+  if (d->collision < LBRT_COLL_IMPLICIT || d->collision > LBRT_COLL_LAMBDA)
+    return fail(LBRT_E_INVAL, "collision = %d is not a collision kind", d->collision);
+  if (d->collision == LBRT_COLL_LAMBDA && d->lambda_iters < 1)
+    return fail(LBRT_E_INVAL, "lambda_iters must be >= 1");
+  if (!std::isfinite(d->lambda_aniso)) return fail(LBRT_E_INVAL, "lambda_aniso not finite");
+  if (d->moving_fluid) {
+    if (d->collision != LBRT_COLL_IMPLICIT)
+      return fail(LBRT_E_UNSUPPORTED, "moving fluid needs the implicit collision");
+    if (d->lambda_aniso != 0.0)
+      return fail(LBRT_E_UNSUPPORTED, "moving fluid supports isotropic scattering only");
+  }
+  double s0 = 0.0, s1[3] = {0, 0, 0}, s2[3][3] = {{0}};
+  for (int i = 0; i < d->ndir; ++i) {
+    const double *n = d->dirs + 3 * i;
+    const double w = d->weights[i];
+    if (!std::isfinite(w) || w == 0.0)
+      return fail(LBRT_E_QUAD, "weight %d = %g must be finite and nonzero", i, w);
+    const double len = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    if (!(std::fabs(len - 1.0) <= 1e-12))
+      return fail(LBRT_E_QUAD, "direction %d has length %.17g, not 1", i, len);
+    s0 += w;
+    for (int a = 0; a < 3; ++a) {
+      s1[a] += w * n[a];
+      for (int b = 0; b < 3; ++b) s2[a][b] += w * n[a] * n[b];
+    }
+    if (d->scale && !(d->scale[i] > 0.0 && std::isfinite(d->scale[i])))
+      return fail(LBRT_E_INVAL, "scale %d = %g must be > 0", i, d->scale[i]);
+  }
+  if (std::fabs(s0 - 1.0) > 1e-12) return fail(LBRT_E_QUAD, "sum w = %.17g, not 1", s0);
+  for (int a = 0; a < 3; ++a) {
+    if (std::fabs(s1[a]) > 1e-12) return fail(LBRT_E_QUAD, "sum w n[%d] = %.3g, not 0", a, s1[a]);
+    for (int b = 0; b < 3; ++b) {
+      const double want = a == b ? 1.0 / 3.0 : 0.0;
+      if (std::fabs(s2[a][b] - want) > 1e-12)
+        return fail(LBRT_E_QUAD, "sum w n n[%d][%d] = %.17g, not %.17g", a, b, s2[a][b], want);
+    }
+  }
+  return LBRT_OK;
+}
+
+int lbrt_init(const lbrt_desc *d, lbrt_ctx **out) {
+  if (!out) return fail(LBRT_E_INVAL, "out is NULL");
+  int rc = lbrt_validate(d);
+  if (rc != LBRT_OK) return rc;
+  lbrt_ctx *c = new lbrt_ctx();
+  c->desc = *d;
+  c->desc.dirs = c->desc.weights = c->desc.scale = nullptr;
+  c->dirs.assign(d->dirs, d->dirs + 3 * d->ndir);
+  c->weights.assign(d->weights, d->weights + d->ndir);
+  c->scales.resize(d->ndir);
+  const bool reduced = d->storage == LBRT_BF16 || d->storage == LBRT_FP16;
+  for (int i = 0; i < d->ndir; ++i)
+    c->scales[i] = reduced ? (d->scale ? d->scale[i] : std::fabs(d->weights[i])) : 1.0;
+  c->bucket = bucket_for(d->ndir);
+  c->nb = kBuckets[c->bucket];
+  // Antipodal pairing (every n_i has a partner -n_i) puts each pair in
+  // adjacent processing slots.
+  std::vector<int> partner(d->ndir, -1);
+  bool paired = (d->ndir % 2) == 0;
+  for (int i = 0; i < d->ndir && paired; ++i) {
+    for (int j = 0; j < d->ndir; ++j) {
+      if (j == i) continue;
+      const double *a = &c->dirs[3 * i], *b = &c->dirs[3 * j];
+      if (std::fabs(a[0] + b[0]) < 1e-12 && std::fabs(a[1] + b[1]) < 1e-12 &&
+          std::fabs(a[2] + b[2]) < 1e-12) {
+        partner[i] = j;
+        break;
+      }
+    }
+    if (partner[i] < 0) paired = false;
+  }
+  c->order.clear();
+  if (paired) {
+    std::vector<bool> used(d->ndir, false);
+    for (int i = 0; i < d->ndir; ++i) {
+      if (used[i]) continue;
+      const int j = partner[i];
+      if (used[j] || partner[j] != i) { paired = false; break; }
+      c->order.push_back(i);
+      c->order.push_back(j);
+      used[i] = used[j] = true;
+    }
+  }
+  if (!paired) {
+    c->order.resize(d->ndir);
+    for (int i = 0; i < d->ndir; ++i) c->order[i] = i;
+  }
+  c->paired = paired;
+  c->tile = default_tile(d->nx, d->ny, d->nz);
+  (void)hipGetDevice(&c->device);
+
+  hipError_t e;
+  size_t tab_bytes;
+  if (d->storage == LBRT_FP64) {
+    std::vector<DirTab<double>> tab;
+    build_table(*c, tab);
+    tab_bytes = sizeof(DirTab<double>) * tab.size();
+    e = hipMalloc(&c->tab_dev, tab_bytes);
+    if (e == hipSuccess) e = hipMemcpy(c->tab_dev, tab.data(), tab_bytes, hipMemcpyHostToDevice);
+  } else {
+    std::vector<DirTab<float>> tab;
+    build_table(*c, tab);
+    tab_bytes = sizeof(DirTab<float>) * tab.size();
+    e = hipMalloc(&c->tab_dev, tab_bytes);
+    if (e == hipSuccess) e = hipMemcpy(c->tab_dev, tab.data(), tab_bytes, hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) e = hipMalloc(&c->scales_dev, sizeof(double) * d->ndir);
+  if (e == hipSuccess)
+    e = hipMemcpy(c->scales_dev, c->scales.data(), sizeof(double) * d->ndir,
+                  hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    rc = fail(e == hipErrorOutOfMemory ? LBRT_E_NOMEM : LBRT_E_HIP, "lbrt_init: %s",
+              hipGetErrorString(e));
+    lbrt_destroy(c);
+    return rc;
+  }
+  KParams p = make_params(c);
+  rc = ensure_partials(c, p.ntiles);
+  if (rc != LBRT_OK) {
+    lbrt_destroy(c);
+    return rc;
+  }
+  *out = c;
+  return LBRT_OK;
+}
+
+void lbrt_destroy(lbrt_ctx *c) {
+  if (!c) return;
+  if (c->tab_dev) (void)hipFree(c->tab_dev);
+  if (c->scales_dev) (void)hipFree(c->scales_dev);
+  if (c->partials) (void)hipFree(c->partials);
+  delete c;
+}
+
+int lbrt_step(lbrt_ctx *c, void *I_a, void *I_b, const float *kappa_a, const float *kappa_s,
+              const float *eta, const float *vel, const lbrt_inflow *inflow, int32_t ninflow,
+              int32_t nsteps, void *E, void *F, double *diag, void *stream) {
+  if (!c) return fail(LBRT_E_INVAL, "ctx is NULL");
+  if (nsteps < 0) return fail(LBRT_E_INVAL, "nsteps = %d < 0", nsteps);
+  if (!I_a || !I_b) return fail(LBRT_E_INVAL, "population buffers are required");
+  if (I_a == I_b) return fail(LBRT_E_INVAL, "I_a and I_b must be distinct (ping-pong)");
+  const lbrt_desc &d = c->desc;
+  const int64_t ncell = (int64_t)d.nx * d.ny * d.nz;
+  const size_t bytes = storage_bytes(d.storage) * (size_t)ncell * d.ndir;
+  const char *a = static_cast<const char *>(I_a), *b = static_cast<const char *>(I_b);
+  if (a < b + bytes && b < a + bytes) return fail(LBRT_E_INVAL, "I_a and I_b overlap");
+  if (!kappa_a || !kappa_s || !eta) return fail(LBRT_E_INVAL, "kappa_a, kappa_s, eta required");
+  if (d.moving_fluid && !vel) return fail(LBRT_E_INVAL, "moving fluid: vel is required");
+  if (!d.moving_fluid && vel) return fail(LBRT_E_INVAL, "vel given but moving_fluid is off");
+  if (ninflow < 0 || ninflow > LBRT_MAX_INFLOW)
+    return fail(LBRT_E_INVAL, "ninflow = %d outside [0, %d]", ninflow, (int)LBRT_MAX_INFLOW);
+  if (ninflow > 0 && !inflow) return fail(LBRT_E_INVAL, "inflow is NULL but ninflow > 0");
+  InflowArgs in{};
+  in.n = ninflow;
+  for (int j = 0; j < ninflow; ++j) {
+    const lbrt_inflow &pl = inflow[j];
+    if (pl.face < 0 || pl.face > 5) return fail(LBRT_E_INVAL, "inflow[%d].face = %d", j, pl.face);
+    if (d.bc[pl.face] != LBRT_BC_INFLOW)
+      return fail(LBRT_E_INVAL, "inflow[%d]: face %d is not an inflow face", j, pl.face);
+    if (pl.dir < 0 || pl.dir >= d.ndir) return fail(LBRT_E_INVAL, "inflow[%d].dir = %d", j, pl.dir);
+    if (!pl.values) return fail(LBRT_E_INVAL, "inflow[%d].values is NULL", j);
+    const int axis = pl.face >> 1;
+    const double comp = c->dirs[3 * pl.dir + axis];
+    const bool enters = (pl.face & 1) == 0 ? comp > 0.0 : comp < 0.0;
+    if (!enters)
+      return fail(LBRT_E_INVAL, "inflow[%d]: direction %d does not enter through face %d", j,
+                  pl.dir, pl.face);
+    for (int k = 0; k < j; ++k)
+      if (in.face[k] == pl.face && in.dir[k] == pl.dir)
+        return fail(LBRT_E_INVAL, "inflow[%d]: (face %d, dir %d) listed twice", j, pl.face,
+                    pl.dir);
+    in.face[j] = pl.face;
+    in.dir[j] = pl.dir;
+    in.ptr[j] = pl.values;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  KParams p = make_params(c);
+  int rc = ensure_partials(c, p.ntiles);
+  if (rc != LBRT_OK) return rc;
+  StepLauncher launch = step_launcher(d.storage, c->bucket);
+  if (!launch) return fail(LBRT_E_UNSUPPORTED, "no kernel for storage %d, %d directions",
+                           d.storage, d.ndir);
+  hipError_t e;
+  if (diag) {
+    e = launch_fill_f64(diag, kDiag, 0.0, s);
+    if (e != hipSuccess) return hip_fail(e, "lbrt_step: clearing diag");
+  }
+  if (nsteps == 0) {
+    if (E || F) return lbrt_moments(c, I_a, E, F, stream);
+    return LBRT_OK;
+  }
+  for (int k = 0; k < nsteps; ++k) {
+    const void *src = (k & 1) ? I_b : I_a;
+    void *dst = (k & 1) ? I_a : I_b;
+    KParams pk = p;
+    const bool last = k == nsteps - 1;
+    if (diag) pk.flags |= KF_DIAG;
+    if (last && (E || F)) pk.flags |= KF_WRITE_EF;
+    e = launch(src, dst, kappa_a, kappa_s, eta, vel, c->tab_dev, pk, in, last ? E : nullptr,
+               last ? F : nullptr, c->partials, s);
+    if (e != hipSuccess) return hip_fail(e, "lbrt_step: launching the step kernel");
+    if (diag) {
+      e = launch_diag_reduce(c->partials, p.ntiles, diag, k == 0, s);
+      if (e != hipSuccess) return hip_fail(e, "lbrt_step: reducing diagnostics");
+    }
+  }
+  return LBRT_OK;
+}
+
+int lbrt_moments(lbrt_ctx *c, const void *I, void *E, void *F, void *stream) {
+  if (!c) return fail(LBRT_E_INVAL, "ctx is NULL");
+  if (!I) return fail(LBRT_E_INVAL, "I is NULL");
+  if (!E && !F) return LBRT_OK;
+  KParams p = make_params(c);
+  hipError_t e = launch_moments(c->desc.storage, I, c->tab_dev, p, E, F,
+                                static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "lbrt_moments");
+  return LBRT_OK;
+}
+
+int lbrt_convert(lbrt_ctx *c, const void *src, int32_t src_storage, void *dst,
+                 int32_t dst_storage, void *stream) {
+  if (!c) return fail(LBRT_E_INVAL, "ctx is NULL");
+  if (!src || !dst) return fail(LBRT_E_INVAL, "src and dst are required");
+  if (src_storage < LBRT_FP32 || src_storage > LBRT_FP16 || dst_storage < LBRT_FP32 ||
+      dst_storage > LBRT_FP16)
+    return fail(LBRT_E_INVAL, "bad storage type");
+  const lbrt_desc &d = c->desc;
+  const int64_t ncell = (int64_t)d.nx * d.ny * d.nz;
+  const size_t sb = storage_bytes(src_storage) * (size_t)ncell * d.ndir;
+  const size_t db = storage_bytes(dst_storage) * (size_t)ncell * d.ndir;
+  const char *a = static_cast<const char *>(src), *b = static_cast<const char *>(dst);
+  if (a < b + db && b < a + sb) return fail(LBRT_E_INVAL, "src and dst overlap");
+  // The context's scales apply to the reduced (BF16/FP16) endpoint.
+  hipError_t e = launch_convert(src, src_storage, dst, dst_storage, c->scales_dev, d.ndir, ncell,
+                                static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "lbrt_convert");
+  return LBRT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,152 @@
+// Small kernels around the fused step: moments of a stored state, storage
+// conversion, deterministic reduction of the per-block diagnostics, fill.
+#include "lbrt_step_kernel.h"
+
+namespace lbrt {
+
+// E = sum_i I_i, F = sum_i n_i I_i (eq. moments_discrete), in the caller's
+// direction order.  The table is walked by storage plane.
+template <typename S>
+__global__ void __launch_bounds__(kBlock)
+moments_kernel(const S *__restrict__ I, const DirTab<typename StoreTraits<S>::T> *__restrict__ tab,
+               int ndir, int64_t ncell, typename StoreTraits<S>::T *__restrict__ E,
+               typename StoreTraits<S>::T *__restrict__ F) {
+  using Tr = StoreTraits<S>;
+  using T = typename Tr::T;
+  const int64_t cell = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (cell >= ncell) return;
+  T e = T(0), f0 = T(0), f1 = T(0), f2 = T(0);
+  for (int i = 0; i < ndir; ++i) {
+    const DirTab<T> &d = tab[i];
+    T v = Tr::ld(I + (int64_t)d.plane * ncell + cell);
+    if (Tr::kReduced) v *= d.scale;
+    e += v;
+    f0 = fma(d.n[0], v, f0);
+    f1 = fma(d.n[1], v, f1);
+    f2 = fma(d.n[2], v, f2);
+  }
+  if (E) E[cell] = e;
+  if (F) {
+    F[cell] = f0;
+    F[ncell + cell] = f1;
+    F[2 * ncell + cell] = f2;
+  }
+}
+
+template <typename S>
+__device__ inline double load_phys(const void *p, int64_t i, double s) {
+  using Tr = StoreTraits<S>;
+  const double v = (double)Tr::ld(static_cast<const S *>(p) + i);
+  return Tr::kReduced ? v * s : v;
+}
+
+template <typename S>
+__device__ inline void store_phys(void *p, int64_t i, double v, double inv_s) {
+  using Tr = StoreTraits<S>;
+  using T = typename Tr::T;
+  Tr::st(static_cast<S *>(p) + i, Tr::kReduced ? (T)(v * inv_s) : (T)v);
+}
+
+__global__ void __launch_bounds__(kBlock)
+convert_kernel(const void *src, int src_storage, void *dst, int dst_storage,
+               const double *__restrict__ scales, int ndir, int64_t ncell) {
+  const int64_t total = ncell * ndir;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * kBlock) {
+    const double s = scales[i / ncell];
+    double v;
+    switch (src_storage) {
+      case LBRT_FP32: v = load_phys<float>(src, i, s); break;
+      case LBRT_FP64: v = load_phys<double>(src, i, s); break;
+      case LBRT_BF16: v = load_phys<bf16_t>(src, i, s); break;
+      default: v = load_phys<f16_t>(src, i, s); break;
+    }
+    switch (dst_storage) {
+      case LBRT_FP32: store_phys<float>(dst, i, v, 1.0 / s); break;
+      case LBRT_FP64: store_phys<double>(dst, i, v, 1.0 / s); break;
+      case LBRT_BF16: store_phys<bf16_t>(dst, i, v, 1.0 / s); break;
+      default: store_phys<f16_t>(dst, i, v, 1.0 / s); break;
+    }
+  }
+}
+
+// Fixed-order reduction of nblocks x kDiag partials: thread t sums blocks
+// t, t + 256, ... in order, then a fixed tree over threads.  Entries 1..7
+// (boundary fluxes) accumulate over steps; 0 and 8 hold the last step.
+__global__ void __launch_bounds__(kBlock)
+diag_reduce_kernel(const double *__restrict__ partials, int nblocks, double *__restrict__ diag,
+                   int first_step) {
+  __shared__ double red[kBlock];
+  for (int j = 0; j < kDiag; ++j) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kBlock) s += partials[(int64_t)b * kDiag + j];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w >= 1; w >>= 1) {
+      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      if (j == 0 || j == 8 || first_step) diag[j] = red[0];
+      else diag[j] += red[0];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void fill_f64_kernel(double *p, int n, double v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_moments(int storage, const void *I, const void *tab, const KParams &p,
+                          void *E, void *F, hipStream_t s) {
+  const int nb = (int)((p.ncell + kBlock - 1) / kBlock);
+  switch (storage) {
+    case LBRT_FP32:
+      hipLaunchKernelGGL(moments_kernel<float>, dim3(nb), dim3(kBlock), 0, s,
+                         static_cast<const float *>(I), static_cast<const DirTab<float> *>(tab),
+                         p.ndir, p.ncell, static_cast<float *>(E), static_cast<float *>(F));
+      break;
+    case LBRT_FP64:
+      hipLaunchKernelGGL(moments_kernel<double>, dim3(nb), dim3(kBlock), 0, s,
+                         static_cast<const double *>(I), static_cast<const DirTab<double> *>(tab),
+                         p.ndir, p.ncell, static_cast<double *>(E), static_cast<double *>(F));
+      break;
+    case LBRT_BF16:
+      hipLaunchKernelGGL(moments_kernel<bf16_t>, dim3(nb), dim3(kBlock), 0, s,
+                         static_cast<const bf16_t *>(I), static_cast<const DirTab<float> *>(tab),
+                         p.ndir, p.ncell, static_cast<float *>(E), static_cast<float *>(F));
+      break;
+    default:
+      hipLaunchKernelGGL(moments_kernel<f16_t>, dim3(nb), dim3(kBlock), 0, s,
+                         static_cast<const f16_t *>(I), static_cast<const DirTab<float> *>(tab),
+                         p.ndir, p.ncell, static_cast<float *>(E), static_cast<float *>(F));
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_convert(const void *src, int src_storage, void *dst, int dst_storage,
+                          const double *scales_dev, int ndir, int64_t ncell, hipStream_t s) {
+  const int64_t total = ncell * ndir;
+  int64_t nb = (total + kBlock - 1) / kBlock;
+  if (nb > 65536) nb = 65536;
+  hipLaunchKernelGGL(convert_kernel, dim3((unsigned)nb), dim3(kBlock), 0, s, src, src_storage,
+                     dst, dst_storage, scales_dev, ndir, ncell);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_reduce(const double *partials, int nblocks, double *diag, int first_step,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(diag_reduce_kernel, dim3(1), dim3(kBlock), 0, s, partials, nblocks, diag,
+                     first_step);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double *p, int n, double v, hipStream_t s) {
+  hipLaunchKernelGGL(fill_f64_kernel, dim3((n + 63) / 64), dim3(64), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace lbrt

@@ -1,0 +1,116 @@
+"""Helpers that run a seeded Problem through the HIP library (GPU tests only)."""
+from __future__ import annotations
+
+import numpy as np
+
+import workloads as wl
+
+
+def torch_mod():
+    import torch
+    return torch
+
+
+def lib():
+    import paper_2007_05718_amd as L
+    return L
+
+
+def pop_torch_dtype(storage):
+    torch = torch_mod()
+    L = lib()
+    return {L.LBRT_FP32: torch.float32, L.LBRT_FP64: torch.float64,
+            L.LBRT_BF16: torch.bfloat16, L.LBRT_FP16: torch.float16}[storage]
+
+
+def host_encoded_state(I0: np.ndarray, weights: np.ndarray, storage: int):
+    """(device tensor in storage format, float64 values the oracle starts from).
+
+    Reduced storage holds I / s with s = w (the default scale); the rounding
+    to the 16-bit format is done on the host by torch's CPU casts."""
+    torch = torch_mod()
+    L = lib()
+    if storage == L.LBRT_FP64:
+        t = torch.from_numpy(np.ascontiguousarray(I0, dtype=np.float64))
+        return t.cuda(), I0.astype(np.float64)
+    if storage == L.LBRT_FP32:
+        h = torch.from_numpy(np.ascontiguousarray(I0, dtype=np.float32))
+        return h.cuda(), h.double().numpy()
+    s = np.abs(weights).reshape((-1,) + (1,) * (I0.ndim - 1))
+    q = torch.from_numpy(np.ascontiguousarray(I0 / s, dtype=np.float32))
+    q16 = q.to(pop_torch_dtype(storage))
+    eff = q16.double().numpy() * s
+    return q16.cuda(), eff
+
+
+def upload_fields(prob):
+    torch = torch_mod()
+    f = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).reshape(-1).cuda()
+    vel = None if prob.vel is None else f(prob.vel)
+    inflow = [(p.face, p.direction, f(p.values)) for p in prob.inflow]
+    return f(prob.kappa_a), f(prob.kappa_s), f(prob.eta), vel, inflow
+
+
+def run_problem(prob, storage=None, steps=None, I0=None, want_diag=True, collision=None,
+                tile=None):
+    """Run ``steps`` GPU steps; returns dict with float64 numpy I (decoded),
+    E, F, diag and the oracle's starting state ``I0_eff``."""
+    import os
+    torch = torch_mod()
+    L = lib()
+    storage = L.LBRT_FP32 if storage is None else storage
+    steps = prob.steps if steps is None else steps
+    kw = {}
+    if collision is not None:
+        kw["collision"] = collision
+    desc = L.Desc.from_problem(prob, storage=storage, **kw)
+    old = os.environ.get("LBRT_TILE")
+    if tile is not None:
+        os.environ["LBRT_TILE"] = tile
+    try:
+        ctx = L.lbrt_init(desc)
+    finally:
+        if tile is not None:
+            if old is None:
+                del os.environ["LBRT_TILE"]
+            else:
+                os.environ["LBRT_TILE"] = old
+    start = prob.I0 if I0 is None else I0
+    Ia, I0_eff = host_encoded_state(np.asarray(start).reshape(prob.ndir, -1), prob.weights,
+                                    storage)
+    Ia = Ia.reshape(-1).contiguous()
+    Ib = torch.empty_like(Ia)
+    ka, ks, eta, vel, inflow = upload_fields(prob)
+    mdt = torch.float64 if storage == L.LBRT_FP64 else torch.float32
+    E = torch.empty(prob.ncell, dtype=mdt, device="cuda")
+    F = torch.empty(3 * prob.ncell, dtype=mdt, device="cuda")
+    diag = torch.zeros(L.LBRT_DIAG_LEN, dtype=torch.float64, device="cuda") if want_diag else None
+    L.lbrt_step(ctx, Ia, Ib, ka, ks, eta, vel=vel, inflow=inflow or None, nsteps=steps,
+                E=E, F=F, diag=diag)
+    out = Ib if steps % 2 == 1 else Ia
+    torch.cuda.synchronize()
+    if storage in (L.LBRT_BF16, L.LBRT_FP16):
+        dec = torch.empty(prob.ndir * prob.ncell, dtype=torch.float32, device="cuda")
+        L.lbrt_convert(ctx, out, storage, dec, L.LBRT_FP32)
+        torch.cuda.synchronize()
+        I = dec.double().cpu().numpy()
+    else:
+        I = out.double().cpu().numpy()
+    res = dict(
+        I=I.reshape((prob.ndir,) + prob.shape),
+        E=E.double().cpu().numpy().reshape(prob.shape),
+        F=F.double().cpu().numpy().reshape((3,) + prob.shape),
+        diag=None if diag is None else diag.cpu().numpy(),
+        I0_eff=I0_eff.reshape((prob.ndir,) + prob.shape),
+        raw=out, ctx=ctx,
+    )
+    return res
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b.ravel())
+    if nb == 0:
+        return float(np.linalg.norm(a.ravel()))
+    return float(np.linalg.norm((a - b).ravel()) / nb)

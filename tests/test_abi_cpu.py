@@ -1,0 +1,90 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry
+point that include/lbrt.h declares, and lbrt_validate (host-only) accepts
+good problem statements and rejects each class of bad one with its code."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    import paper_2007_05718_amd as L
+    return L
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "lbrt.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbrt_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    names = declared_functions()
+    assert "lbrt_step" in names and "lbrt_init" in names
+    lib = L.library()
+    for n in names:
+        assert hasattr(lib, n), n
+    for n in L.exported_symbols():
+        assert n in names
+
+
+def _desc(**kw):
+    L = _lib()
+    dirs, w = wl.lebedev(50)
+    args = dict(nx=16, ny=12, nz=10, dt=0.5, dirs=dirs, weights=w)
+    args.update(kw)
+    return L.Desc(**args)
+
+
+def test_validate_accepts_good_descriptions():
+    L = _lib()
+    assert L.lbrt_validate(_desc()) == L.LBRT_OK
+    assert L.lbrt_validate(_desc(dt=1.0)) == L.LBRT_OK
+    assert L.lbrt_validate(_desc(storage=L.LBRT_BF16)) == L.LBRT_OK
+    assert L.lbrt_validate(_desc(moving_fluid=True)) == L.LBRT_OK
+    assert L.lbrt_validate(_desc(bc=(1, 1, 0, 2, 1, 1))) == L.LBRT_OK
+    for n in (6, 14, 26, 38, 74, 86, 110, 146):
+        dirs, w = wl.lebedev(n)
+        assert L.lbrt_validate(_desc(dirs=dirs, weights=w)) == L.LBRT_OK
+
+
+def test_validate_rejects_bad_descriptions():
+    L = _lib()
+    dirs, w = wl.lebedev(50)
+    assert L.lbrt_validate(_desc(dt=1.01)) == L.LBRT_E_CFL
+    assert L.lbrt_validate(_desc(dt=0.0)) == L.LBRT_E_CFL
+    assert L.lbrt_validate(_desc(nx=1)) == L.LBRT_E_INVAL
+    assert L.lbrt_validate(_desc(weights=w * 1.001)) == L.LBRT_E_QUAD
+    bad = dirs.copy()
+    bad[0] *= 1.01
+    assert L.lbrt_validate(_desc(dirs=bad)) == L.LBRT_E_QUAD
+    shifted = dirs.copy()
+    shifted[:, 0] += 0.0
+    ww = w.copy()
+    ww[0] += 1e-6
+    ww[1] -= 1e-6                      # sum still 1, first moment broken
+    assert L.lbrt_validate(_desc(weights=ww)) == L.LBRT_E_QUAD
+    assert L.lbrt_validate(_desc(bc=(1, 0, 0, 0, 0, 0))) == L.LBRT_E_INVAL
+    assert L.lbrt_validate(_desc(bc=(3, 3, 0, 0, 0, 0))) == L.LBRT_E_INVAL
+    assert L.lbrt_validate(_desc(storage=7)) == L.LBRT_E_INVAL
+    assert L.lbrt_validate(_desc(collision=5)) == L.LBRT_E_INVAL
+    assert L.lbrt_validate(_desc(collision=L.LBRT_COLL_LAMBDA, lambda_iters=0)) == L.LBRT_E_INVAL
+    assert (L.lbrt_validate(_desc(moving_fluid=True, collision=L.LBRT_COLL_EXPLICIT))
+            == L.LBRT_E_UNSUPPORTED)
+    assert L.lbrt_validate(_desc(moving_fluid=True, lam=0.5)) == L.LBRT_E_UNSUPPORTED
+    assert L.lbrt_validate(_desc(scale=-np.ones(50))) == L.LBRT_E_INVAL
+    # a rule that is not exact to degree 2 (Gauss-type points perturbed)
+    rng = np.random.default_rng(0)
+    r = rng.standard_normal((40, 3))
+    r /= np.linalg.norm(r, axis=1, keepdims=True)
+    assert L.lbrt_validate(_desc(dirs=r, weights=np.full(40, 1 / 40))) == L.LBRT_E_QUAD
+    # too many directions
+    assert L.lbrt_validate(_desc(dirs=np.tile(dirs, (4, 1)), weights=np.tile(w, 4) / 4)) \
+        == L.LBRT_E_INVAL
+    assert "ndir" in L.lbrt_last_error()
