@@ -131,6 +131,24 @@ def kernel_only_ms(L, torch, prob, storage, steps):
     return float(np.mean(ms))
 
 
+def copy_ceiling_gbs(torch, nbytes: int = 4 << 30, reps: int = 10) -> float:
+    """Read+write bandwidth of a plain device-to-device copy (torch's copy kernel)."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / reps
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(prob, planes: int = 16):
     """FP64 oracle, one step on a slab of `planes` z-planes of the workload."""
     import copy
@@ -217,6 +235,8 @@ def main():
             "hbm_GBs_algorithmic": round(b2 / (k2 * 1e-3) / 1e9, 1),
             "speedup_vs_fp32": round(wall / w2, 3),
         }
+    log("copy ceiling")
+    copy_gbs = copy_ceiling_gbs(torch)
     cpu = None
     if not args.no_cpu:
         log("timing the oracle on the host")
@@ -253,6 +273,7 @@ def main():
             "kernel": "step_kernel<float,110>",
             "kernel_ms": round(kms, 4),
             "bytes_per_launch_algorithmic": bytes_launch,
+            "copy_kernel_GBs": round(copy_gbs, 1),
         },
         "cpu_baseline": cpu,
         "forms": forms,

@@ -60,6 +60,9 @@ class LbrtError(RuntimeError):
 
 
 def _load():
+    # torch's bundled HIP runtime must be the one in the process: importing
+    # torch first makes the library bind to it rather than to a second copy.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"lbrt HIP library missing at {LIB_PATH}; build it with "
                           "`python -m paper_2007_05718_amd.build`")

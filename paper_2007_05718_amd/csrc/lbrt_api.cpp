@@ -12,23 +12,6 @@
 
 #include "lbrt_internal.h"
 
-namespace lbrt {
-StepLauncher step_launcher_f32(int);
-StepLauncher step_launcher_f64(int);
-StepLauncher step_launcher_bf16(int);
-StepLauncher step_launcher_f16(int);
-
-StepLauncher step_launcher(int storage, int bucket_index) {
-  switch (storage) {
-    case LBRT_FP32: return step_launcher_f32(bucket_index);
-    case LBRT_FP64: return step_launcher_f64(bucket_index);
-    case LBRT_BF16: return step_launcher_bf16(bucket_index);
-    case LBRT_FP16: return step_launcher_f16(bucket_index);
-    default: return nullptr;
-  }
-}
-}  // namespace lbrt
-
 using namespace lbrt;
 
 namespace {
@@ -71,9 +54,14 @@ struct lbrt_ctx {
   void *tab_dev = nullptr;        // DirTab<float> or DirTab<double>, nb entries
   void *tab_moments_dev = nullptr;
   double *scales_dev = nullptr;   // per storage plane
-  double *partials = nullptr;     // per-block diagnostics
+  double *partials = nullptr;     // per-block sums of the step kernel
   int partials_cap = 0;
+  double *face_partials = nullptr;  // per-block boundary fluxes
+  InflowArgs *inflow_dev = nullptr; // ghost-plane table of the current call
+  InflowArgs inflow_host{};         // what inflow_dev holds
+  bool inflow_valid = false;
   TileShape tile{64, 4, 1};
+  int slab = 0;                   // y-blocks per sweep slab (0: default)
   int device = 0;
 };
 
@@ -96,14 +84,15 @@ int bucket_for(int ndir) {
 TileShape default_tile(int nx, int ny, int nz) {
   if (const char *env = std::getenv("LBRT_TILE")) {
     TileShape t{};
-    if (std::sscanf(env, "%dx%dx%d", &t.tx, &t.ty, &t.tz) == 3 && t.tx * t.ty * t.tz == kBlock)
+    if (std::sscanf(env, "%dx%dx%d", &t.tx, &t.ty, &t.tz) == 3 && t.tx > 0 && t.ty > 0 &&
+        t.tz > 0 && t.tx * t.ty * t.tz == kTileCells)
       return t;
   }
   (void)ny;
   (void)nz;
-  if (nx >= 64) return {64, 4, 1};
-  if (nx >= 32) return {32, 8, 1};
-  return {16, 16, 1};
+  if (nx >= 64) return {64, 1, 1};
+  if (nx >= 32) return {32, 2, 1};
+  return {16, 4, 1};
 }
 
 template <typename T>
@@ -112,11 +101,14 @@ void build_table(const lbrt_ctx &c, std::vector<DirTab<T>> &tab) {
   tab.assign(c.nb, DirTab<T>{});
   const double dx = d.dx, dt = d.dt;
   const int64_t sy = d.nx, sz = (int64_t)d.nx * d.ny;
+  const int64_t ncell = (int64_t)d.nx * d.ny * d.nz;
+  const int64_t esize = (int64_t)storage_bytes(d.storage);
   for (int k = 0; k < c.nb; ++k) {
     DirTab<T> &e = tab[k];
     std::memset(&e, 0, sizeof(e));
-    if (k >= d.ndir) {  // null direction: loads its own cell of plane order[0], weight 0
+    if (k >= d.ndir) {  // null direction: reads its own cell of plane order[0] with weight 0
       e.plane = c.order[0];
+      e.plane_off = (int64_t)e.plane * ncell * esize;
       e.scale = T(1);
       e.inv_scale = T(1);
       continue;
@@ -136,7 +128,7 @@ void build_table(const lbrt_ctx &c, std::vector<DirTab<T>> &tab) {
       const double wy = by ? delta[1] : 1.0 - delta[1];
       const double wz = bz ? delta[2] : 1.0 - delta[2];
       e.tw[b] = (T)(wx * wy * wz);
-      e.off[b] = (int32_t)(-(bx * s[0] + by * s[1] * sy + bz * s[2] * sz));
+      e.off[b] = (int32_t)(-(bx * s[0] + by * s[1] * sy + bz * s[2] * sz) * esize);
     }
     e.w = (T)c.weights[i];
     for (int a = 0; a < 3; ++a) {
@@ -147,6 +139,7 @@ void build_table(const lbrt_ctx &c, std::vector<DirTab<T>> &tab) {
     e.scale = (T)c.scales[i];
     e.inv_scale = (T)(1.0 / c.scales[i]);
     e.plane = i;
+    e.plane_off = (int64_t)i * ncell * esize;
   }
 }
 
@@ -155,7 +148,7 @@ int ensure_partials(lbrt_ctx *c, int nblocks) {
   if (c->partials) (void)hipFree(c->partials);
   c->partials = nullptr;
   c->partials_cap = 0;
-  hipError_t e = hipMalloc(&c->partials, sizeof(double) * kDiag * (size_t)nblocks);
+  hipError_t e = hipMalloc(&c->partials, sizeof(double) * kStepPartials * (size_t)nblocks);
   if (e != hipSuccess) return fail(LBRT_E_NOMEM, "hipMalloc(diagnostic partials): %s",
                                    hipGetErrorString(e));
   c->partials_cap = nblocks;
@@ -177,8 +170,10 @@ KParams make_params(const lbrt_ctx *c) {
   p.nty = (d.ny + p.ty - 1) / p.ty;
   p.ntz = (d.nz + p.tz - 1) / p.tz;
   p.ntiles = p.ntx * p.nty * p.ntz;
+  // slab height: about 16 cell rows (a slab-plane of all directions fits L2)
+  p.slab = c->slab > 0 ? c->slab : std::max(1, 16 / p.ty);
+  if (p.slab > p.nty) p.slab = p.nty;
   for (int a = 0; a < 3; ++a) p.periodic[a] = d.bc[2 * a] == LBRT_BC_PERIODIC;
-  for (int f = 0; f < 6; ++f) p.inflow_face[f] = d.bc[f] == LBRT_BC_INFLOW;
   p.mode = d.collision;
   p.lambda_iters = d.lambda_iters;
   p.flags = 0;
@@ -274,6 +269,13 @@ int lbrt_init(const lbrt_desc *d, lbrt_ctx **out) {
     c->scales[i] = reduced ? (d->scale ? d->scale[i] : std::fabs(d->weights[i])) : 1.0;
   c->bucket = bucket_for(d->ndir);
   c->nb = kBuckets[c->bucket];
+  if (!step_launcher(d->storage, c->bucket, d->moving_fluid != 0)) {
+    rc = fail(LBRT_E_UNSUPPORTED,
+              "no compiled kernel for storage %d with %d directions (%s fluid)", d->storage,
+              d->ndir, d->moving_fluid ? "moving" : "static");
+    delete c;
+    return rc;
+  }
   // Antipodal pairing (every n_i has a partner -n_i) puts each pair in
   // adjacent processing slots.
   std::vector<int> partner(d->ndir, -1);
@@ -308,6 +310,7 @@ int lbrt_init(const lbrt_desc *d, lbrt_ctx **out) {
   }
   c->paired = paired;
   c->tile = default_tile(d->nx, d->ny, d->nz);
+  if (const char *env = std::getenv("LBRT_SLAB")) c->slab = std::atoi(env);
   (void)hipGetDevice(&c->device);
 
   hipError_t e;
@@ -337,6 +340,11 @@ int lbrt_init(const lbrt_desc *d, lbrt_ctx **out) {
   }
   KParams p = make_params(c);
   rc = ensure_partials(c, p.ntiles);
+  if (rc == LBRT_OK) {
+    e = hipMalloc(&c->face_partials, sizeof(double) * kFacePartials * (size_t)face_flux_blocks(p));
+    if (e == hipSuccess) e = hipMalloc(&c->inflow_dev, sizeof(InflowArgs));
+    if (e != hipSuccess) rc = fail(LBRT_E_NOMEM, "hipMalloc(context buffers): %s", hipGetErrorString(e));
+  }
   if (rc != LBRT_OK) {
     lbrt_destroy(c);
     return rc;
@@ -350,6 +358,8 @@ void lbrt_destroy(lbrt_ctx *c) {
   if (c->tab_dev) (void)hipFree(c->tab_dev);
   if (c->scales_dev) (void)hipFree(c->scales_dev);
   if (c->partials) (void)hipFree(c->partials);
+  if (c->face_partials) (void)hipFree(c->face_partials);
+  if (c->inflow_dev) (void)hipFree(c->inflow_dev);
   delete c;
 }
 
@@ -371,7 +381,8 @@ int lbrt_step(lbrt_ctx *c, void *I_a, void *I_b, const float *kappa_a, const flo
   if (ninflow < 0 || ninflow > LBRT_MAX_INFLOW)
     return fail(LBRT_E_INVAL, "ninflow = %d outside [0, %d]", ninflow, (int)LBRT_MAX_INFLOW);
   if (ninflow > 0 && !inflow) return fail(LBRT_E_INVAL, "inflow is NULL but ninflow > 0");
-  InflowArgs in{};
+  InflowArgs in;
+  std::memset(&in, 0, sizeof(in));
   in.n = ninflow;
   for (int j = 0; j < ninflow; ++j) {
     const lbrt_inflow &pl = inflow[j];
@@ -394,11 +405,36 @@ int lbrt_step(lbrt_ctx *c, void *I_a, void *I_b, const float *kappa_a, const flo
     in.dir[j] = pl.dir;
     in.ptr[j] = pl.values;
   }
+  // per processing slot and axis: the ghost plane that slot pulls from
+  for (int k = 0; k < LBRT_MAX_DIRS; ++k)
+    for (int a = 0; a < 3; ++a) in.ghost[k][a] = nullptr;
+  bool xghosts = false;
+  for (int j = 0; j < ninflow; ++j) xghosts |= (in.face[j] >> 1) == 0;
+  for (int k = 0; k < d.ndir; ++k) {
+    const int i = c->order[k];
+    for (int a = 0; a < 3; ++a) {
+      const double comp = c->dirs[3 * i + a];
+      if (comp == 0.0) continue;
+      const int face = 2 * a + (comp > 0.0 ? 0 : 1);
+      for (int j = 0; j < ninflow; ++j)
+        if (in.face[j] == face && in.dir[j] == i) in.ghost[k][a] = in.ptr[j];
+    }
+  }
   hipStream_t s = static_cast<hipStream_t>(stream);
   KParams p = make_params(c);
+  if (xghosts) p.flags |= KF_XGHOSTS;
   int rc = ensure_partials(c, p.ntiles);
   if (rc != LBRT_OK) return rc;
-  StepLauncher launch = step_launcher(d.storage, c->bucket);
+  // The ghost table lives in device memory; it is re-sent (in stream order,
+  // from pageable memory, so the host copy may change right after) only when
+  // this call's planes differ from the previous call's.
+  if (!c->inflow_valid || std::memcmp(&c->inflow_host, &in, sizeof(in)) != 0) {
+    hipError_t e0 = hipMemcpyAsync(c->inflow_dev, &in, sizeof(in), hipMemcpyHostToDevice, s);
+    if (e0 != hipSuccess) return hip_fail(e0, "lbrt_step: uploading the inflow table");
+    c->inflow_host = in;
+    c->inflow_valid = true;
+  }
+  StepLauncher launch = step_launcher(d.storage, c->bucket, d.moving_fluid != 0);
   if (!launch) return fail(LBRT_E_UNSUPPORTED, "no kernel for storage %d, %d directions",
                            d.storage, d.ndir);
   hipError_t e;
@@ -415,13 +451,19 @@ int lbrt_step(lbrt_ctx *c, void *I_a, void *I_b, const float *kappa_a, const flo
     void *dst = (k & 1) ? I_a : I_b;
     KParams pk = p;
     const bool last = k == nsteps - 1;
-    if (diag) pk.flags |= KF_DIAG;
+    int face_blocks = 0;
+    if (diag) {
+      pk.flags |= KF_DIAG;
+      e = launch_face_flux(d.storage, src, c->tab_dev, pk, c->inflow_dev, c->face_partials,
+                           &face_blocks, s);
+      if (e != hipSuccess) return hip_fail(e, "lbrt_step: launching the face-flux kernel");
+    }
     if (last && (E || F)) pk.flags |= KF_WRITE_EF;
-    e = launch(src, dst, kappa_a, kappa_s, eta, vel, c->tab_dev, pk, in, last ? E : nullptr,
+    e = launch(src, dst, kappa_a, kappa_s, eta, vel, c->tab_dev, pk, c->inflow_dev, last ? E : nullptr,
                last ? F : nullptr, c->partials, s);
     if (e != hipSuccess) return hip_fail(e, "lbrt_step: launching the step kernel");
     if (diag) {
-      e = launch_diag_reduce(c->partials, p.ntiles, diag, k == 0, s);
+      e = launch_diag_reduce(c->partials, p.ntiles, c->face_partials, face_blocks, diag, k == 0, s);
       if (e != hipSuccess) return hip_fail(e, "lbrt_step: reducing diagnostics");
     }
   }

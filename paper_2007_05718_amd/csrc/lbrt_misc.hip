@@ -4,8 +4,8 @@
 
 namespace lbrt {
 
-// E = sum_i I_i, F = sum_i n_i I_i (eq. moments_discrete), in the caller's
-// direction order.  The table is walked by storage plane.
+// E = sum_i I_i, F = sum_i n_i I_i (eq. moments_discrete), summed in the
+// table's processing order.
 template <typename S>
 __global__ void __launch_bounds__(kBlock)
 moments_kernel(const S *__restrict__ I, const DirTab<typename StoreTraits<S>::T> *__restrict__ tab,
@@ -70,27 +70,36 @@ convert_kernel(const void *src, int src_storage, void *dst, int dst_storage,
   }
 }
 
-// Fixed-order reduction of nblocks x kDiag partials: thread t sums blocks
-// t, t + 256, ... in order, then a fixed tree over threads.  Entries 1..7
-// (boundary fluxes) accumulate over steps; 0 and 8 hold the last step.
+// Fixed-order reduction of the per-block partials into diag: block j of the
+// grid reduces entry j.  Thread t sums blocks t, t + 256, ... in order, then a
+// fixed tree over threads; the result does not depend on timing.  Entries
+// 1..7 (boundary fluxes, from the face kernel) accumulate over steps; 0 and 8
+// (sums of E and E*, from the step kernel) hold the last step.
 __global__ void __launch_bounds__(kBlock)
-diag_reduce_kernel(const double *__restrict__ partials, int nblocks, double *__restrict__ diag,
-                   int first_step) {
+diag_reduce_kernel(const double *__restrict__ step_partials, int step_blocks,
+                   const double *__restrict__ face_partials, int face_blocks,
+                   double *__restrict__ diag, int first_step) {
   __shared__ double red[kBlock];
-  for (int j = 0; j < kDiag; ++j) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += kBlock) s += partials[(int64_t)b * kDiag + j];
-    red[threadIdx.x] = s;
+  const int j = blockIdx.x;   // diag entry
+  const double *src;
+  int n, stride, col;
+  if (j == 0 || j == 8) {
+    src = step_partials; n = step_blocks; stride = kStepPartials; col = j == 0 ? 0 : 1;
+  } else {
+    src = face_partials; n = face_blocks; stride = kFacePartials; col = j - 1;
+  }
+  double s = 0.0;
+  if (src != nullptr)
+    for (int b = threadIdx.x; b < n; b += kBlock) s += src[(int64_t)b * stride + col];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kBlock / 2; w >= 1; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
-    for (int w = kBlock / 2; w >= 1; w >>= 1) {
-      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      if (j == 0 || j == 8 || first_step) diag[j] = red[0];
-      else diag[j] += red[0];
-    }
-    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (j == 0 || j == 8 || first_step) diag[j] = red[0];
+    else diag[j] += red[0];
   }
 }
 
@@ -137,10 +146,11 @@ hipError_t launch_convert(const void *src, int src_storage, void *dst, int dst_s
   return hipGetLastError();
 }
 
-hipError_t launch_diag_reduce(const double *partials, int nblocks, double *diag, int first_step,
-                              hipStream_t s) {
-  hipLaunchKernelGGL(diag_reduce_kernel, dim3(1), dim3(kBlock), 0, s, partials, nblocks, diag,
-                     first_step);
+hipError_t launch_diag_reduce(const double *step_partials, int step_blocks,
+                              const double *face_partials, int face_blocks, double *diag,
+                              int first_step, hipStream_t s) {
+  hipLaunchKernelGGL(diag_reduce_kernel, dim3(kDiag), dim3(kBlock), 0, s, step_partials,
+                     step_blocks, face_partials, face_blocks, diag, first_step);
   return hipGetLastError();
 }
 

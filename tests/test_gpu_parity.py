@@ -130,11 +130,16 @@ def test_exact_shift_is_bit_exact():
         assert np.array_equal(res["I"][i], ref)
 
 
-def test_tile_shapes_are_bit_identical():
-    p = wl.random_problem(41, shape=(12, 16, 140), npoints=50, steps=2,
-                          bc=(wl.BC_PERIODIC, wl.BC_PERIODIC) + (wl.BC_OUTFLOW,) * 4)
-    ref = gh.run_problem(p, storage=L().LBRT_FP32, tile="64x4x1")
-    for tile in ("32x8x1", "16x4x4", "64x2x2", "32x4x2", "64x1x4"):
+@pytest.mark.parametrize("bc,planes", [
+    ((wl.BC_PERIODIC, wl.BC_PERIODIC) + (wl.BC_OUTFLOW,) * 4, 0),
+    ((wl.BC_INFLOW, wl.BC_INFLOW, wl.BC_INFLOW, wl.BC_OUTFLOW, wl.BC_PERIODIC, wl.BC_PERIODIC), 6),
+])
+def test_tile_shapes_are_bit_identical(bc, planes):
+    """Tile shape changes which cells take the boundary path; results must not move."""
+    p = wl.random_problem(41, shape=(12, 16, 140), npoints=50, steps=2, bc=bc,
+                          inflow_planes=planes)
+    ref = gh.run_problem(p, storage=L().LBRT_FP32, tile="64x1x1")
+    for tile in ("32x2x1", "16x4x1", "16x2x2", "8x8x1", "16x1x4", "4x4x4"):
         got = gh.run_problem(p, storage=L().LBRT_FP32, tile=tile)
         assert np.array_equal(got["I"], ref["I"]), tile
         assert np.array_equal(got["E"], ref["E"]), tile
