@@ -40,7 +40,7 @@ size_t storage_bytes(int s) {
   }
 }
 
-struct TileShape { int tx, ty, tz; };
+struct TileShape { int tx, ty; };
 
 }  // namespace
 
@@ -56,12 +56,17 @@ struct lbrt_ctx {
   double *scales_dev = nullptr;   // per storage plane
   double *partials = nullptr;     // per-block sums of the step kernel
   int partials_cap = 0;
-  double *face_partials = nullptr;  // per-block boundary fluxes
   InflowArgs *inflow_dev = nullptr; // ghost-plane table of the current call
   InflowArgs inflow_host{};         // what inflow_dev holds
   bool inflow_valid = false;
-  TileShape tile{64, 4, 1};
-  int slab = 0;                   // y-blocks per sweep slab (0: default)
+  TileShape tile{64, 1};
+  int zlen = 64;                  // z-planes per block of the main kernel
+  int zlen_general = 8;           // z-planes per block of the general kernel
+  // General-kernel tile lists (device, int4 per block), for calls without
+  // (index 0) and with (index 1) inflow ghost planes on a z face.
+  int4 *general_dev[2] = {nullptr, nullptr};
+  int ngeneral[2] = {0, 0};
+  int main_zr0[2] = {0, 0}, main_nzr[2] = {0, 0};
   int device = 0;
 };
 
@@ -84,23 +89,40 @@ int bucket_for(int ndir) {
 TileShape default_tile(int nx, int ny, int nz) {
   if (const char *env = std::getenv("LBRT_TILE")) {
     TileShape t{};
-    if (std::sscanf(env, "%dx%dx%d", &t.tx, &t.ty, &t.tz) == 3 && t.tx > 0 && t.ty > 0 &&
-        t.tz > 0 && t.tx * t.ty * t.tz == kTileCells)
+    if (std::sscanf(env, "%dx%d", &t.tx, &t.ty) == 2 && t.tx > 0 && t.ty > 0 &&
+        t.tx * t.ty == kTileCells && (t.tx & (t.tx - 1)) == 0)
       return t;
   }
   (void)ny;
   (void)nz;
-  if (nx >= 64) return {64, 1, 1};
-  if (nx >= 32) return {32, 2, 1};
-  return {16, 4, 1};
+  if (nx >= 64) return {64, 1};
+  if (nx >= 32) return {32, 2};
+  if (nx >= 16) return {16, 4};
+  return {8, 8};
 }
 
+// z-planes marched by one block: long enough that the prologue plane (one
+// extra plane per range) is cheap, short enough that the grid has several
+// blocks per CU.
+int default_zlen(int nx, int ny, int nz, const TileShape &t) {
+  if (const char *env = std::getenv("LBRT_ZLEN")) {
+    const int v = std::atoi(env);
+    if (v > 0) return v;
+  }
+  const int64_t xy_tiles = (int64_t)((nx + t.tx - 1) / t.tx) * ((ny + t.ty - 1) / t.ty);
+  // aim for about 4096 blocks (16 per CU) but never fewer than 16 planes
+  int64_t ranges = (4096 + xy_tiles - 1) / xy_tiles;
+  int zlen = (int)std::max<int64_t>(16, (nz + ranges - 1) / ranges);
+  return std::min(zlen, nz);
+}
+
+// Direction table in processing order: nb slots (directions, then null
+// slots), stored twice (the step kernel reads copy z & 1 on plane z).
 template <typename T>
 void build_table(const lbrt_ctx &c, std::vector<DirTab<T>> &tab) {
   const lbrt_desc &d = c.desc;
-  tab.assign(c.nb, DirTab<T>{});
+  tab.assign(2 * (size_t)c.nb, DirTab<T>{});
   const double dx = d.dx, dt = d.dt;
-  const int64_t sy = d.nx, sz = (int64_t)d.nx * d.ny;
   const int64_t ncell = (int64_t)d.nx * d.ny * d.nz;
   const int64_t esize = (int64_t)storage_bytes(d.storage);
   for (int k = 0; k < c.nb; ++k) {
@@ -108,9 +130,12 @@ void build_table(const lbrt_ctx &c, std::vector<DirTab<T>> &tab) {
     std::memset(&e, 0, sizeof(e));
     if (k >= d.ndir) {  // null direction: reads its own cell of plane order[0] with weight 0
       e.plane = c.order[0];
+      e.plane_el = (int64_t)e.plane * ncell;
       e.plane_off = (int64_t)e.plane * ncell * esize;
       e.scale = T(1);
       e.inv_scale = T(1);
+      e.wx[0] = e.wy[0] = T(1);
+      e.wz_new = T(1);
       continue;
     }
     const int i = c.order[k];
@@ -128,8 +153,22 @@ void build_table(const lbrt_ctx &c, std::vector<DirTab<T>> &tab) {
       const double wy = by ? delta[1] : 1.0 - delta[1];
       const double wz = bz ? delta[2] : 1.0 - delta[2];
       e.tw[b] = (T)(wx * wy * wz);
-      e.off[b] = (int32_t)(-(bx * s[0] + by * s[1] * sy + bz * s[2] * sz) * esize);
     }
+    e.wx[0] = (T)(1.0 - delta[0]);
+    e.wx[1] = (T)delta[0];
+    e.wy[0] = (T)(1.0 - delta[1]);
+    e.wy[1] = (T)delta[1];
+    // z weights in march order: (new plane, carried plane)
+    e.wz_new = (T)(s[2] < 0 ? delta[2] : 1.0 - delta[2]);
+    e.wz_old = (T)(s[2] < 0 ? 1.0 - delta[2] : delta[2]);
+    e.dxs = (T)(delta[0] * c.scales[i]);
+    e.cxp = (T)(s[0] > 0 ? 1.0 : 0.0);
+    e.cxm = (T)(s[0] < 0 ? 1.0 : 0.0);
+    e.mxp = s[0] > 0 ? 0xffffffffu : 0u;
+    e.mxm = s[0] < 0 ? 0xffffffffu : 0u;
+    e.dzn = s[2] < 0 ? 1 : 0;
+    e.active = 1;
+    e.row_shift = -s[1] * d.nx;
     e.w = (T)c.weights[i];
     for (int a = 0; a < 3; ++a) {
       e.n[a] = (T)n[a];
@@ -139,8 +178,10 @@ void build_table(const lbrt_ctx &c, std::vector<DirTab<T>> &tab) {
     e.scale = (T)c.scales[i];
     e.inv_scale = (T)(1.0 / c.scales[i]);
     e.plane = i;
+    e.plane_el = (int64_t)i * ncell;
     e.plane_off = (int64_t)i * ncell * esize;
   }
+  for (int k = 0; k < c.nb; ++k) tab[c.nb + k] = tab[k];
 }
 
 int ensure_partials(lbrt_ctx *c, int nblocks) {
@@ -165,14 +206,19 @@ KParams make_params(const lbrt_ctx *c) {
   p.ncell = (int64_t)d.nx * d.ny * d.nz;
   p.tx = c->tile.tx;
   p.ty = c->tile.ty;
-  p.tz = c->tile.tz;
-  p.ntx = (d.nx + p.tx - 1) / p.tx;
+  p.txlog = 0;
+  while ((1 << p.txlog) < p.tx) ++p.txlog;
+  p.zlen = c->zlen;
+  // main kernel: full x tiles, y tiles whose halo rows are inside the box
+  p.ntx = d.nx / p.tx;
   p.nty = (d.ny + p.ty - 1) / p.ty;
-  p.ntz = (d.nz + p.tz - 1) / p.tz;
-  p.ntiles = p.ntx * p.nty * p.ntz;
-  // slab height: about 16 cell rows (a slab-plane of all directions fits L2)
-  p.slab = c->slab > 0 ? c->slab : std::max(1, 16 / p.ty);
-  if (p.slab > p.nty) p.slab = p.nty;
+  p.main_ty0 = 1;
+  p.main_nty = std::max(0, (d.ny - 1 - p.ty) / p.ty);
+  p.main_zr0 = c->main_zr0[0];
+  p.main_nzr = c->main_nzr[0];
+  p.nblocks = p.ntx * p.main_nty * p.main_nzr;
+  p.ngeneral = c->ngeneral[0];
+  p.general_list = c->general_dev[0];
   for (int a = 0; a < 3; ++a) p.periodic[a] = d.bc[2 * a] == LBRT_BC_PERIODIC;
   p.mode = d.collision;
   p.lambda_iters = d.lambda_iters;
@@ -185,6 +231,53 @@ KParams make_params(const lbrt_ctx *c) {
   return p;
 }
 
+
+// Splits the tiles between the main kernel (interior rows, full x tiles, z
+// ranges of zlen planes) and the general kernel (everything else, in z ranges
+// of zlen_general planes).  With zinflow, the first/last z range (next to a z
+// face with inflow ghost planes) also goes to the general kernel.
+int plan_tiles(lbrt_ctx *c, int variant, bool zlo_inflow, bool zhi_inflow) {
+  const lbrt_desc &d = c->desc;
+  const int tx = c->tile.tx, ty = c->tile.ty;
+  const int ntx_full = d.nx / tx, ntx_all = (d.nx + tx - 1) / tx;
+  const int nty = (d.ny + ty - 1) / ty;
+  const int main_nty = std::max(0, (d.ny - 1 - ty) / ty);
+  const int nzr = (d.nz + c->zlen - 1) / c->zlen;
+  int zr0 = zlo_inflow ? 1 : 0;
+  int zr1 = nzr - (zhi_inflow ? 1 : 0);
+  if (zr1 < zr0 || ntx_full == 0 || main_nty == 0) zr1 = zr0;
+  c->main_zr0[variant] = zr0;
+  c->main_nzr[variant] = zr1 - zr0;
+  const bool any_main = zr1 > zr0;
+  std::vector<int4> list;
+  auto add_column = [&](int tix, int tiy, int z0, int z1) {
+    for (int zb = z0; zb < z1; zb += c->zlen_general)
+      list.push_back(make_int4(tix * tx, tiy * ty, zb, std::min(z1, zb + c->zlen_general)));
+  };
+  for (int tiy = 0; tiy < nty; ++tiy) {
+    for (int tix = 0; tix < ntx_all; ++tix) {
+      const bool main_xy = any_main && tix < ntx_full && tiy >= 1 && tiy <= main_nty;
+      if (!main_xy) {
+        add_column(tix, tiy, 0, d.nz);
+      } else {
+        add_column(tix, tiy, 0, std::min(d.nz, zr0 * c->zlen));
+        add_column(tix, tiy, std::min(d.nz, zr1 * c->zlen), d.nz);
+      }
+    }
+  }
+  c->ngeneral[variant] = (int)list.size();
+  if (c->general_dev[variant]) (void)hipFree(c->general_dev[variant]);
+  c->general_dev[variant] = nullptr;
+  if (list.empty()) return LBRT_OK;
+  hipError_t e = hipMalloc(&c->general_dev[variant], sizeof(int4) * list.size());
+  if (e == hipSuccess)
+    e = hipMemcpy(c->general_dev[variant], list.data(), sizeof(int4) * list.size(),
+                  hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(LBRT_E_NOMEM, "tile list: %s", hipGetErrorString(e));
+  return LBRT_OK;
+}
+
+int total_partials(const KParams &p) { return p.nblocks + p.ngeneral + zface_blocks(p); }
 }  // namespace
 
 extern "C" {
@@ -197,8 +290,8 @@ int lbrt_validate(const lbrt_desc *d) {
     return fail(LBRT_E_INVAL, "grid %d x %d x %d: every dimension must be >= 2", d->nx, d->ny,
                 d->nz);
   const int64_t ncell = (int64_t)d->nx * d->ny * d->nz;
-  if (ncell >= (int64_t)1 << 31 || (int64_t)d->nx * d->ny >= (int64_t)1 << 30)
-    return fail(LBRT_E_INVAL, "grid too large: ncell must be < 2^31");
+  if (ncell >= (int64_t)1 << 31 || (int64_t)d->nx * d->ny >= (int64_t)1 << 28)
+    return fail(LBRT_E_INVAL, "grid too large: nx*ny*nz must be < 2^31 and nx*ny < 2^28");
   if (!(d->dx > 0.0) || !std::isfinite(d->dx)) return fail(LBRT_E_INVAL, "dx must be > 0");
   if (!(d->dt > 0.0) || !std::isfinite(d->dt)) return fail(LBRT_E_CFL, "dt must be > 0");
   if (d->dt > d->dx)
@@ -310,7 +403,11 @@ int lbrt_init(const lbrt_desc *d, lbrt_ctx **out) {
   }
   c->paired = paired;
   c->tile = default_tile(d->nx, d->ny, d->nz);
-  if (const char *env = std::getenv("LBRT_SLAB")) c->slab = std::atoi(env);
+  c->zlen = default_zlen(d->nx, d->ny, d->nz, c->tile);
+  if (const char *env = std::getenv("LBRT_ZLEN_GENERAL")) {
+    const int v = std::atoi(env);
+    if (v > 0) c->zlen_general = v;
+  }
   (void)hipGetDevice(&c->device);
 
   hipError_t e;
@@ -338,11 +435,19 @@ int lbrt_init(const lbrt_desc *d, lbrt_ctx **out) {
     lbrt_destroy(c);
     return rc;
   }
-  KParams p = make_params(c);
-  rc = ensure_partials(c, p.ntiles);
+  rc = plan_tiles(c, 0, false, false);
   if (rc == LBRT_OK) {
-    e = hipMalloc(&c->face_partials, sizeof(double) * kFacePartials * (size_t)face_flux_blocks(p));
-    if (e == hipSuccess) e = hipMalloc(&c->inflow_dev, sizeof(InflowArgs));
+    const bool zlo = d->bc[LBRT_FACE_MZ] == LBRT_BC_INFLOW, zhi = d->bc[LBRT_FACE_PZ] == LBRT_BC_INFLOW;
+    rc = (zlo || zhi) ? plan_tiles(c, 1, zlo, zhi) : plan_tiles(c, 1, false, false);
+  }
+  if (rc != LBRT_OK) {
+    lbrt_destroy(c);
+    return rc;
+  }
+  KParams p = make_params(c);
+  rc = ensure_partials(c, total_partials(p));
+  if (rc == LBRT_OK) {
+    e = hipMalloc(&c->inflow_dev, sizeof(InflowArgs));
     if (e != hipSuccess) rc = fail(LBRT_E_NOMEM, "hipMalloc(context buffers): %s", hipGetErrorString(e));
   }
   if (rc != LBRT_OK) {
@@ -358,8 +463,9 @@ void lbrt_destroy(lbrt_ctx *c) {
   if (c->tab_dev) (void)hipFree(c->tab_dev);
   if (c->scales_dev) (void)hipFree(c->scales_dev);
   if (c->partials) (void)hipFree(c->partials);
-  if (c->face_partials) (void)hipFree(c->face_partials);
   if (c->inflow_dev) (void)hipFree(c->inflow_dev);
+  for (int v = 0; v < 2; ++v)
+    if (c->general_dev[v]) (void)hipFree(c->general_dev[v]);
   delete c;
 }
 
@@ -408,8 +514,11 @@ int lbrt_step(lbrt_ctx *c, void *I_a, void *I_b, const float *kappa_a, const flo
   // per processing slot and axis: the ghost plane that slot pulls from
   for (int k = 0; k < LBRT_MAX_DIRS; ++k)
     for (int a = 0; a < 3; ++a) in.ghost[k][a] = nullptr;
-  bool xghosts = false;
-  for (int j = 0; j < ninflow; ++j) xghosts |= (in.face[j] >> 1) == 0;
+  bool xghosts = false, zghosts = false;
+  for (int j = 0; j < ninflow; ++j) {
+    xghosts |= (in.face[j] >> 1) == 0;
+    zghosts |= (in.face[j] >> 1) == 2;
+  }
   for (int k = 0; k < d.ndir; ++k) {
     const int i = c->order[k];
     for (int a = 0; a < 3; ++a) {
@@ -423,7 +532,15 @@ int lbrt_step(lbrt_ctx *c, void *I_a, void *I_b, const float *kappa_a, const flo
   hipStream_t s = static_cast<hipStream_t>(stream);
   KParams p = make_params(c);
   if (xghosts) p.flags |= KF_XGHOSTS;
-  int rc = ensure_partials(c, p.ntiles);
+  if (zghosts) {
+    // z ranges next to an inflow z face go to the general kernel
+    p.main_zr0 = c->main_zr0[1];
+    p.main_nzr = c->main_nzr[1];
+    p.nblocks = p.ntx * p.main_nty * p.main_nzr;
+    p.ngeneral = c->ngeneral[1];
+    p.general_list = c->general_dev[1];
+  }
+  int rc = ensure_partials(c, total_partials(p));
   if (rc != LBRT_OK) return rc;
   // The ghost table lives in device memory; it is re-sent (in stream order,
   // from pageable memory, so the host copy may change right after) only when
@@ -451,19 +568,19 @@ int lbrt_step(lbrt_ctx *c, void *I_a, void *I_b, const float *kappa_a, const flo
     void *dst = (k & 1) ? I_a : I_b;
     KParams pk = p;
     const bool last = k == nsteps - 1;
-    int face_blocks = 0;
+    const int nparts = total_partials(p);
     if (diag) {
       pk.flags |= KF_DIAG;
-      e = launch_face_flux(d.storage, src, c->tab_dev, pk, c->inflow_dev, c->face_partials,
-                           &face_blocks, s);
-      if (e != hipSuccess) return hip_fail(e, "lbrt_step: launching the face-flux kernel");
+      e = launch_zface(d.storage, src, c->tab_dev, p, c->inflow_dev,
+                       c->partials + (size_t)(p.nblocks + p.ngeneral) * kStepPartials, s);
+      if (e != hipSuccess) return hip_fail(e, "lbrt_step: launching the z-face flux kernel");
     }
     if (last && (E || F)) pk.flags |= KF_WRITE_EF;
-    e = launch(src, dst, kappa_a, kappa_s, eta, vel, c->tab_dev, pk, c->inflow_dev, last ? E : nullptr,
-               last ? F : nullptr, c->partials, s);
+    e = launch(src, dst, kappa_a, kappa_s, eta, vel, c->tab_dev, pk, c->inflow_dev,
+               last ? E : nullptr, last ? F : nullptr, c->partials, s);
     if (e != hipSuccess) return hip_fail(e, "lbrt_step: launching the step kernel");
     if (diag) {
-      e = launch_diag_reduce(c->partials, p.ntiles, c->face_partials, face_blocks, diag, k == 0, s);
+      e = launch_diag_reduce(c->partials, nparts, diag, k == 0, s);
       if (e != hipSuccess) return hip_fail(e, "lbrt_step: reducing diagnostics");
     }
   }

@@ -18,7 +18,22 @@ struct f16_t { uint16_t u; };
 template <typename T>
 struct DirTab {
   T tw[8];          // trilinear tap weights, tap b = bx | by << 1 | bz << 2 (eq. interp)
-  int32_t off[8];   // byte offset of tap b from its cell: -(bx sx + by sy nx + bz sz nx ny) * size
+  // The same weights per axis: wx = (1 - delta_x, delta_x), likewise wy; the
+  // z pair is stored as (weight of the newly loaded plane, weight of the
+  // carried plane) in the z-march order: (1 - delta_z, delta_z) when
+  // s_z >= 0, (delta_z, 1 - delta_z) when s_z < 0.
+  T wx[2], wy[2];
+  T wz_new, wz_old;
+  T dxs;            // delta_x * scale: x-face outflux per stored unit
+  // Main-path constants of the z-march: sx > 0 / sx < 0 as 0/1 factors and
+  // as all-ones/zero masks, the new plane's z offset (1 when sz < 0), and the
+  // element shift of the y-halo row (-sy * nx).
+  T cxp, cxm;
+  uint32_t mxp, mxm;
+  int32_t dzn;
+  int32_t row_shift;
+  int32_t active;   // 1 for a direction, 0 for a null (padding) slot
+  int64_t plane_el; // element offset of the direction's plane: plane * ncell
   int64_t plane_off;// byte offset of the direction's plane: plane * ncell * size
   T w;              // quadrature weight
   T n[3];           // unit direction
@@ -54,10 +69,17 @@ struct KParams {
   int32_t nx, ny, nz;
   int32_t ndir;
   int64_t ncell;
-  int32_t tx, ty, tz;          // tile shape in cells (tx * ty * tz == 64)
-  int32_t ntx, nty, ntz;       // tiles per axis
-  int32_t ntiles;
-  int32_t slab;                // y-blocks per slab of the tile sweep
+  int32_t tx, ty;              // xy tile in cells (tx * ty == 64, tx a power of two)
+  int32_t txlog;               // log2(tx)
+  int32_t ntx, nty;            // tiles per axis
+  int32_t zlen;                // z-planes marched by one block of the main kernel
+  // Main kernel tiles: x tiles [0, ntx), y tiles [main_ty0, main_ty0 + main_nty),
+  // z ranges [main_zr0, main_zr0 + main_nzr); nblocks = ntx * main_nty * main_nzr.
+  int32_t main_ty0, main_nty, main_zr0, main_nzr;
+  int32_t nblocks;
+  // General kernel: one block per (x0, y0, zb, ze) entry.
+  int32_t ngeneral;
+  const int4 *general_list;
   int32_t periodic[3];         // per axis x, y, z
   int32_t mode;                // lbrt_collision
   int32_t lambda_iters;
@@ -68,15 +90,16 @@ struct KParams {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;   // waves per block = direction quarters
-constexpr int kTileCells = 64;        // cells per block tile (one per lane)
+constexpr int kTileCells = 64;        // cells per xy tile (one per lane)
 constexpr int kDiag = LBRT_DIAG_LEN;
-constexpr int kStepPartials = 2;   // per block: sum E, sum E*
-constexpr int kFacePartials = 7;   // per block: outflux on 6 faces, influx
+// Per-block diagnostic partials of the step kernel: sum E, sum E*, outflux
+// through the faces -x, +x, -y, +y, -z, +z, influx from inflow ghosts.
+constexpr int kStepPartials = 9;
 
 // Direction-count buckets with a compiled kernel (multiples of 8: four waves
 // times pairs).  Rules whose size is not a bucket run in the next larger
 // bucket, padded with null directions.
-constexpr int kBuckets[] = {16, 32, 56, 64, 112, 128, 152, 160};
+constexpr int kBuckets[] = {16, 32, 56, 112, 152};
 constexpr int kNumBuckets = sizeof(kBuckets) / sizeof(kBuckets[0]);
 
 // Launchers, one per (storage, bucket), defined in lbrt_step_*.hip.
@@ -92,15 +115,16 @@ hipError_t launch_moments(int storage, const void *I, const void *tab, const KPa
                           void *E, void *F, hipStream_t s);
 hipError_t launch_convert(const void *src, int src_storage, void *dst, int dst_storage,
                           const double *scales_dev, int ndir, int64_t ncell, hipStream_t s);
-// Boundary fluxes of a state (outflux per face, inflow influx) into
-// per-block partials; returns the number of blocks used in *nblocks.
-hipError_t launch_face_flux(int storage, const void *I, const void *tab, const KParams &p,
-                            const InflowArgs *inflow, double *partials, int *nblocks,
-                            hipStream_t s);
-int face_flux_blocks(const KParams &p);
-hipError_t launch_diag_reduce(const double *step_partials, int step_blocks,
-                              const double *face_partials, int face_blocks, double *diag,
-                              int first_step, hipStream_t s);
+// Reduces the step kernel's per-block partials (nblocks rows of
+// kStepPartials) into diag in a fixed order: sums of E and E* replace diag[0]
+// and diag[8]; fluxes are added to diag[1..7] (replaced when first_step).
+hipError_t launch_diag_reduce(const double *partials, int nblocks, double *diag, int first_step,
+                              hipStream_t s);
 hipError_t launch_fill_f64(double *p, int n, double v, hipStream_t s);
+// Blocks of the z-face flux kernel (0 on a periodic z axis), and its launch:
+// per-block partials in the step kernel's format.
+int zface_blocks(const KParams &p);
+hipError_t launch_zface(int storage, const void *I, const void *tab, const KParams &p,
+                        const InflowArgs *inflow, double *partials, hipStream_t s);
 
 }  // namespace lbrt

@@ -70,27 +70,20 @@ convert_kernel(const void *src, int src_storage, void *dst, int dst_storage,
   }
 }
 
-// Fixed-order reduction of the per-block partials into diag: block j of the
-// grid reduces entry j.  Thread t sums blocks t, t + 256, ... in order, then a
-// fixed tree over threads; the result does not depend on timing.  Entries
-// 1..7 (boundary fluxes, from the face kernel) accumulate over steps; 0 and 8
-// (sums of E and E*, from the step kernel) hold the last step.
+// Fixed-order reduction of the step kernel's per-block partials into diag:
+// block j of the grid reduces entry j.  Thread t sums blocks t, t + 256, ...
+// in order, then a fixed tree over threads, so the result does not depend on
+// timing.  Entries 1..7 (boundary fluxes) accumulate over steps; 0 and 8
+// (sums of E and E*) hold the last step.
 __global__ void __launch_bounds__(kBlock)
-diag_reduce_kernel(const double *__restrict__ step_partials, int step_blocks,
-                   const double *__restrict__ face_partials, int face_blocks,
-                   double *__restrict__ diag, int first_step) {
+diag_reduce_kernel(const double *__restrict__ partials, int nblocks, double *__restrict__ diag,
+                   int first_step) {
   __shared__ double red[kBlock];
   const int j = blockIdx.x;   // diag entry
-  const double *src;
-  int n, stride, col;
-  if (j == 0 || j == 8) {
-    src = step_partials; n = step_blocks; stride = kStepPartials; col = j == 0 ? 0 : 1;
-  } else {
-    src = face_partials; n = face_blocks; stride = kFacePartials; col = j - 1;
-  }
+  // partial columns: 0 sum E, 1 sum E*, 2..7 outflux per face, 8 influx
+  const int col = j == 0 ? 0 : (j == 8 ? 1 : (j == 7 ? 8 : j + 1));
   double s = 0.0;
-  if (src != nullptr)
-    for (int b = threadIdx.x; b < n; b += kBlock) s += src[(int64_t)b * stride + col];
+  for (int b = threadIdx.x; b < nblocks; b += kBlock) s += partials[(int64_t)b * kStepPartials + col];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = kBlock / 2; w >= 1; w >>= 1) {
@@ -146,11 +139,44 @@ hipError_t launch_convert(const void *src, int src_storage, void *dst, int dst_s
   return hipGetLastError();
 }
 
-hipError_t launch_diag_reduce(const double *step_partials, int step_blocks,
-                              const double *face_partials, int face_blocks, double *diag,
-                              int first_step, hipStream_t s) {
-  hipLaunchKernelGGL(diag_reduce_kernel, dim3(kDiag), dim3(kBlock), 0, s, step_partials,
-                     step_blocks, face_partials, face_blocks, diag, first_step);
+hipError_t launch_diag_reduce(const double *partials, int nblocks, double *diag, int first_step,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(diag_reduce_kernel, dim3(kDiag), dim3(kBlock), 0, s, partials, nblocks, diag,
+                     first_step);
+  return hipGetLastError();
+}
+
+int zface_blocks(const KParams &p) {
+  if (p.periodic[2]) return 0;
+  return (int)((2 * (int64_t)p.nx * p.ny + kBlock - 1) / kBlock);
+}
+
+hipError_t launch_zface(int storage, const void *I, const void *tab, const KParams &p,
+                        const InflowArgs *inflow, double *partials, hipStream_t s) {
+  const int nb = zface_blocks(p);
+  if (nb == 0) return hipSuccess;
+  switch (storage) {
+    case LBRT_FP32:
+      hipLaunchKernelGGL(zface_kernel<float>, dim3(nb), dim3(kBlock), 0, s,
+                         static_cast<const float *>(I), static_cast<const DirTab<float> *>(tab),
+                         p, inflow, partials);
+      break;
+    case LBRT_FP64:
+      hipLaunchKernelGGL(zface_kernel<double>, dim3(nb), dim3(kBlock), 0, s,
+                         static_cast<const double *>(I),
+                         static_cast<const DirTab<double> *>(tab), p, inflow, partials);
+      break;
+    case LBRT_BF16:
+      hipLaunchKernelGGL(zface_kernel<bf16_t>, dim3(nb), dim3(kBlock), 0, s,
+                         static_cast<const bf16_t *>(I), static_cast<const DirTab<float> *>(tab),
+                         p, inflow, partials);
+      break;
+    default:
+      hipLaunchKernelGGL(zface_kernel<f16_t>, dim3(nb), dim3(kBlock), 0, s,
+                         static_cast<const f16_t *>(I), static_cast<const DirTab<float> *>(tab),
+                         p, inflow, partials);
+      break;
+  }
   return hipGetLastError();
 }
 

@@ -4,18 +4,14 @@
 namespace lbrt {
 
 StepLauncher launcher_f32_16_static();
-StepLauncher launcher_f32_32_static();
-StepLauncher launcher_f32_56_static();
-StepLauncher launcher_f32_64_static();
-StepLauncher launcher_f32_112_static();
-StepLauncher launcher_f32_128_static();
-StepLauncher launcher_f32_152_static();
-StepLauncher launcher_f32_160_static();
 StepLauncher launcher_f32_16_moving();
+StepLauncher launcher_f32_32_static();
 StepLauncher launcher_f32_32_moving();
+StepLauncher launcher_f32_56_static();
 StepLauncher launcher_f32_56_moving();
-StepLauncher launcher_f32_64_moving();
+StepLauncher launcher_f32_112_static();
 StepLauncher launcher_f32_112_moving();
+StepLauncher launcher_f32_152_static();
 StepLauncher launcher_f32_152_moving();
 StepLauncher launcher_f64_16_static();
 StepLauncher launcher_f64_16_moving();
@@ -23,41 +19,33 @@ StepLauncher launcher_f64_32_static();
 StepLauncher launcher_f64_32_moving();
 StepLauncher launcher_f64_56_static();
 StepLauncher launcher_f64_56_moving();
-StepLauncher launcher_f64_64_static();
-StepLauncher launcher_f64_64_moving();
 StepLauncher launcher_bf16_16_static();
 StepLauncher launcher_bf16_32_static();
 StepLauncher launcher_bf16_56_static();
-StepLauncher launcher_bf16_64_static();
+StepLauncher launcher_bf16_56_moving();
 StepLauncher launcher_bf16_112_static();
 StepLauncher launcher_bf16_152_static();
-StepLauncher launcher_bf16_56_moving();
 StepLauncher launcher_bf16_152_moving();
 StepLauncher launcher_f16_16_static();
 StepLauncher launcher_f16_32_static();
 StepLauncher launcher_f16_56_static();
-StepLauncher launcher_f16_64_static();
+StepLauncher launcher_f16_56_moving();
 StepLauncher launcher_f16_112_static();
 StepLauncher launcher_f16_152_static();
-StepLauncher launcher_f16_56_moving();
 StepLauncher launcher_f16_152_moving();
 
 StepLauncher step_launcher(int storage, int bucket_index, bool moving) {
   if (bucket_index < 0 || bucket_index >= kNumBuckets) return nullptr;
   const int nb = kBuckets[bucket_index];
   if (storage == LBRT_FP32 && nb == 16 && moving == false) return launcher_f32_16_static();
-  if (storage == LBRT_FP32 && nb == 32 && moving == false) return launcher_f32_32_static();
-  if (storage == LBRT_FP32 && nb == 56 && moving == false) return launcher_f32_56_static();
-  if (storage == LBRT_FP32 && nb == 64 && moving == false) return launcher_f32_64_static();
-  if (storage == LBRT_FP32 && nb == 112 && moving == false) return launcher_f32_112_static();
-  if (storage == LBRT_FP32 && nb == 128 && moving == false) return launcher_f32_128_static();
-  if (storage == LBRT_FP32 && nb == 152 && moving == false) return launcher_f32_152_static();
-  if (storage == LBRT_FP32 && nb == 160 && moving == false) return launcher_f32_160_static();
   if (storage == LBRT_FP32 && nb == 16 && moving == true) return launcher_f32_16_moving();
+  if (storage == LBRT_FP32 && nb == 32 && moving == false) return launcher_f32_32_static();
   if (storage == LBRT_FP32 && nb == 32 && moving == true) return launcher_f32_32_moving();
+  if (storage == LBRT_FP32 && nb == 56 && moving == false) return launcher_f32_56_static();
   if (storage == LBRT_FP32 && nb == 56 && moving == true) return launcher_f32_56_moving();
-  if (storage == LBRT_FP32 && nb == 64 && moving == true) return launcher_f32_64_moving();
+  if (storage == LBRT_FP32 && nb == 112 && moving == false) return launcher_f32_112_static();
   if (storage == LBRT_FP32 && nb == 112 && moving == true) return launcher_f32_112_moving();
+  if (storage == LBRT_FP32 && nb == 152 && moving == false) return launcher_f32_152_static();
   if (storage == LBRT_FP32 && nb == 152 && moving == true) return launcher_f32_152_moving();
   if (storage == LBRT_FP64 && nb == 16 && moving == false) return launcher_f64_16_static();
   if (storage == LBRT_FP64 && nb == 16 && moving == true) return launcher_f64_16_moving();
@@ -65,23 +53,19 @@ StepLauncher step_launcher(int storage, int bucket_index, bool moving) {
   if (storage == LBRT_FP64 && nb == 32 && moving == true) return launcher_f64_32_moving();
   if (storage == LBRT_FP64 && nb == 56 && moving == false) return launcher_f64_56_static();
   if (storage == LBRT_FP64 && nb == 56 && moving == true) return launcher_f64_56_moving();
-  if (storage == LBRT_FP64 && nb == 64 && moving == false) return launcher_f64_64_static();
-  if (storage == LBRT_FP64 && nb == 64 && moving == true) return launcher_f64_64_moving();
   if (storage == LBRT_BF16 && nb == 16 && moving == false) return launcher_bf16_16_static();
   if (storage == LBRT_BF16 && nb == 32 && moving == false) return launcher_bf16_32_static();
   if (storage == LBRT_BF16 && nb == 56 && moving == false) return launcher_bf16_56_static();
-  if (storage == LBRT_BF16 && nb == 64 && moving == false) return launcher_bf16_64_static();
+  if (storage == LBRT_BF16 && nb == 56 && moving == true) return launcher_bf16_56_moving();
   if (storage == LBRT_BF16 && nb == 112 && moving == false) return launcher_bf16_112_static();
   if (storage == LBRT_BF16 && nb == 152 && moving == false) return launcher_bf16_152_static();
-  if (storage == LBRT_BF16 && nb == 56 && moving == true) return launcher_bf16_56_moving();
   if (storage == LBRT_BF16 && nb == 152 && moving == true) return launcher_bf16_152_moving();
   if (storage == LBRT_FP16 && nb == 16 && moving == false) return launcher_f16_16_static();
   if (storage == LBRT_FP16 && nb == 32 && moving == false) return launcher_f16_32_static();
   if (storage == LBRT_FP16 && nb == 56 && moving == false) return launcher_f16_56_static();
-  if (storage == LBRT_FP16 && nb == 64 && moving == false) return launcher_f16_64_static();
+  if (storage == LBRT_FP16 && nb == 56 && moving == true) return launcher_f16_56_moving();
   if (storage == LBRT_FP16 && nb == 112 && moving == false) return launcher_f16_112_static();
   if (storage == LBRT_FP16 && nb == 152 && moving == false) return launcher_f16_152_static();
-  if (storage == LBRT_FP16 && nb == 56 && moving == true) return launcher_f16_56_moving();
   if (storage == LBRT_FP16 && nb == 152 && moving == true) return launcher_f16_152_moving();
   return nullptr;
 }

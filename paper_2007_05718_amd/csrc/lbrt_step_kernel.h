@@ -1,27 +1,39 @@
-// Fused stream-and-collide kernel for gfx950.
+// Fused stream-and-collide kernel for gfx950: a z-march over xy tiles.
 //
-// A block of 256 threads owns a tile of 64 cells (TX x TY x TZ, x fastest).
-// Its four wave64s split the directions: wave q streams the q-th quarter of
-// the direction slots for all 64 cells, one cell per lane, and keeps those
-// streamed values in registers.  A step therefore reads each stored population
-// once from HBM (the other seven taps of the trilinear pull hit L1/L2) and
-// writes it once:
-//   stream   trilinear pull of eq. (interp) from the 2x2x2 upwind cells,
+// A block of 256 threads owns an xy tile of 64 cells (tx x ty, x fastest, one
+// cell per lane) and marches it through a range of z-planes.  Its four wave64s
+// split the directions: wave q streams the q-th quarter of the direction slots
+// for the tile's 64 cells and keeps the streamed values in registers.
+//
+// The trilinear pull of eq. (interp) is separable.  With the plane value
+//   P_i(x, y, z') = (1-dy)[(1-dx) I(x, y, z') + dx I(x-sx, y, z')]
+//                 +   dy [(1-dx) I(x, y-sy, z') + dx I(x-sx, y-sy, z')],
+// the streamed population is  I*_i(z) = (1-dz) P_i(z) + dz P_i(z - sz).
+// Marching up in z, each (direction, plane) value P is computed once and
+// carried in a register to the next plane: a direction with sz > 0 reuses
+// P(z-1) from the previous plane and computes P(z); one with sz < 0 reuses P(z)
+// and computes P(z+1).  A plane costs four row loads per direction (two rows,
+// each unshifted and x-shifted), all at a wave-uniform base address plus the
+// lane's byte offset, so the address arithmetic is scalar.
+//
+// Per plane:
+//   stream   the quarter of the directions, P from 4 row loads, I* from P and
+//            the carried plane;
 //   moments  per-wave partial E*, F* (eq. moments_discrete), combined across
-//            the four waves through LDS in a fixed order,
+//            the four waves through LDS in a fixed order;
 //   collide  per-cell closed form of the chosen collision (Sec. 3.3, App. B),
-//            evaluated by every wave,
-//   store    each wave its quarter of the new populations; wave 0 also E, F
-//            and the energy sums.
-// Splitting directions over waves (rather than cells over lanes) keeps every
-// direction constant wave-uniform (scalar registers) and cuts the registers a
-// thread needs for its streamed values by four, which is what lets enough
-// waves stay resident to cover HBM latency.
+//            evaluated by every wave;
+//   store    each wave its quarter of the new populations; wave 0 also E, F.
+// Energy diagnostics (sums of E and E*, the outflux through each face and the
+// influx from inflow ghosts) accumulate per lane over the march and end as
+// per-block partials in FP64.
 //
-// Boundaries: the x faces are resolved per lane inside the main path (a lane
-// on a face re-targets its x-shifted taps to a wrapped or in-cell address and
-// swaps in the vacuum or inflow ghost value), so only tiles whose y or z halo
-// leaves the box, and ragged tiles, take the per-tap checked path.
+// Boundaries: x faces are resolved per lane (the x-shifted load of a face lane
+// is re-targeted to the wrapped cell, or to its own cell and zeroed), planes
+// outside the box in z come from the inflow ghost plane or are vacuum, and
+// tiles whose y halo leaves the box (or with ragged lanes) take a per-tap
+// checked path.  Inflow ghosts on x faces enter through a separate correction
+// term after the vacuum sums, so every path computes the same value.
 #pragma once
 
 #include <utility>
@@ -78,42 +90,49 @@ template <> struct StoreTraits<f16_t> {
   }
 };
 
+// Load at a wave-uniform base plus a lane's byte offset.
 template <typename S>
-__device__ inline typename StoreTraits<S>::T ld_byte(const char *base, uint32_t byte_off) {
-  return StoreTraits<S>::ld(reinterpret_cast<const S *>(base + byte_off));
+__device__ __forceinline__ typename StoreTraits<S>::T ldo(const S *base, uint32_t byte_off) {
+  return StoreTraits<S>::ld(
+      reinterpret_cast<const S *>(reinterpret_cast<const char *>(base) + byte_off));
 }
 
 template <typename T> __device__ inline T rcp(T x);
 template <> __device__ inline float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 template <> __device__ inline double rcp<double>(double x) { return 1.0 / x; }
 
+// Unrolled loop helper: calls f.template operator()<J>() for J = 0..N-1.
+template <int J, int N, typename F>
+__device__ __forceinline__ void unroll(F &f) {
+  if constexpr (J < N) {
+    f.template operator()<J>();
+    unroll<J + 1, N>(f);
+  }
+}
+
+// w0 u + w1 v, in one fixed rounding order used by every path.
+template <typename T>
+__device__ __forceinline__ T lerp2(T w0, T w1, T u, T v) {
+  return fma(w1, v, w0 * u);
+}
+
+// Plane value from its four taps (x, y), (x-sx, y), (x, y-sy), (x-sx, y-sy).
+template <typename T>
+__device__ __forceinline__ T interp4(const DirTab<T> &d, T a, T a1, T b, T b1) {
+  return lerp2(d.wy[0], d.wy[1], lerp2(d.wx[0], d.wx[1], a, a1), lerp2(d.wx[0], d.wx[1], b, b1));
+}
+
 // ---------------------------------------------------------------------------
-// Block id -> tile.  Tiles are numbered along a sweep that keeps neighbours
-// close in time: the box is cut into slabs of `slab` y-blocks; a slab is swept
-// z-plane by z-plane, each plane y-block by y-block, x fastest.  The tile that
-// needs a row of plane z-1 (or of the previous y-block) ran only a slab-plane
-// earlier, so the row is still in L2.  The hardware deals block ids round-robin
-// to the eight XCDs (each with its own L2); XCD x takes the x-th contiguous run
-// of the sweep.
+// Block id -> (x tile, y tile, z range).  The hardware deals block ids
+// round-robin to the eight XCDs (each with its own L2); XCD k takes the k-th
+// contiguous run of the tile order (x fastest, then y, then z range), so the
+// blocks resident on one XCD hold neighbouring rows of the same z range and
+// share their y-halo rows in that XCD's L2.
 // ---------------------------------------------------------------------------
 __device__ inline int xcd_tile(int bid, int ntiles) {
   const int per = ntiles >> 3, rem = ntiles & 7;
   const int xcd = bid & 7, k = bid >> 3;
   return xcd * per + min(xcd, rem) + k;
-}
-
-__device__ inline void sweep_tile(int t, int ntx, int nty, int ntz, int slab, int &tix,
-                                  int &tiy, int &tiz) {
-  const int slab_tiles = ntx * slab * ntz;
-  const int s = t / slab_tiles;
-  int r = t - s * slab_tiles;
-  const int yb0 = s * slab;
-  const int nyb = min(slab, nty - yb0);   // the last slab may be thinner
-  const int plane = ntx * nyb;
-  tiz = r / plane;
-  r -= tiz * plane;
-  tiy = yb0 + r / ntx;
-  tix = r - (r / ntx) * ntx;
 }
 
 __device__ inline double wave_sum(double v) {
@@ -141,115 +160,141 @@ __device__ inline void block_sums(const double (&v)[M], double *out) {
   }
 }
 
+__device__ __forceinline__ int wrap(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
+
 // ---------------------------------------------------------------------------
-// Checked stream of one direction at one in-box cell: periodic wrap, inflow
-// ghosts (a point outside along exactly one axis) and vacuum elsewhere.
+// Outflux booking of one population of a cell on a non-periodic face: the
+// fraction dt |n^a| / dx of the population leaves through the face of axis a
+// (eq. interp); leaving along several axes, the part outside in x is booked on
+// the x face, of the rest the part outside in y on the y face, the rest on the
+// z face.  zlo/zhi: the cell's plane is the low/high z face.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void book_outflux(const DirTab<T> &d, T own, bool lox, bool hix,
+                                             bool loy, bool hiy, bool zlo, bool zhi, T &fx, T &fy,
+                                             T &fzlo, T &fzhi) {
+  T stay = T(1);
+  const bool lx = d.s[0] > 0 ? hix : (d.s[0] < 0 ? lox : false);
+  fx += lx ? d.delta[0] * own : T(0);
+  stay = lx ? d.wx[0] : stay;
+  const bool ly = d.s[1] > 0 ? hiy : (d.s[1] < 0 ? loy : false);
+  fy += ly ? stay * d.delta[1] * own : T(0);
+  stay = ly ? stay * d.wy[0] : stay;
+  const T oz = stay * d.delta[2] * own;
+  fzhi += (d.s[2] > 0 && zhi) ? oz : T(0);
+  fzlo += (d.s[2] < 0 && zlo) ? oz : T(0);
+}
+
+// ---------------------------------------------------------------------------
+// Plane value on the checked path: plane zl inside the box; each of the four
+// taps is wrapped on periodic axes, read inside the box, taken from the y-face
+// inflow ghost plane ([z][x] layout) when it is outside in y only, and vacuum
+// otherwise (x-face ghosts enter later through x_ghost_correction).  `own`
+// gets the unshifted tap (the cell's own stored value).
 // ---------------------------------------------------------------------------
 template <typename S>
 __device__ __forceinline__ typename StoreTraits<S>::T
-stream_checked(const S *__restrict__ P, const DirTab<typename StoreTraits<S>::T> &d, int x,
-               int y, int z, int nx, int ny, int nz, int px, int py, int pz,
-               const float *gx, const float *gy, const float *gz) {
+checked_P(const DirTab<typename StoreTraits<S>::T> &d, const S *__restrict__ pl, int x, int y,
+          bool valid, int nx, int ny, int perx, int pery, const float *gy, int zl,
+          typename StoreTraits<S>::T &own) {
   using Tr = StoreTraits<S>;
   using T = typename Tr::T;
-  T v[8];
+  T v[4];
 #pragma unroll
-  for (int b = 0; b < 8; ++b) {
+  for (int b = 0; b < 4; ++b) {
     int cx = x - (b & 1) * d.s[0];
-    int cy = y - ((b >> 1) & 1) * d.s[1];
-    int cz = z - (b >> 2) * d.s[2];
-    if (px) cx = cx < 0 ? cx + nx : (cx >= nx ? cx - nx : cx);
-    if (py) cy = cy < 0 ? cy + ny : (cy >= ny ? cy - ny : cy);
-    if (pz) cz = cz < 0 ? cz + nz : (cz >= nz ? cz - nz : cz);
+    int cy = y - (b >> 1) * d.s[1];
+    if (perx) cx = wrap(cx, nx);
+    if (pery) cy = wrap(cy, ny);
     const bool ox = (unsigned)cx >= (unsigned)nx;
     const bool oy = (unsigned)cy >= (unsigned)ny;
-    const bool oz = (unsigned)cz >= (unsigned)nz;
-    const int nout = (int)ox + (int)oy + (int)oz;
     T val = T(0);
-    if (nout == 0) {
-      val = Tr::ld(P + ((int64_t)cz * ny + cy) * nx + cx);
-    } else if (nout == 1) {
-      const float *g = ox ? gx : (oy ? gy : gz);
-      if (g != nullptr) {
-        const int64_t gi = ox ? (int64_t)cz * ny + cy
-                              : (oy ? (int64_t)cz * nx + cx : (int64_t)cy * nx + cx);
-        const T gv = (T)g[gi];
+    if (valid) {
+      if (!ox && !oy) {
+        val = Tr::ld(pl + (int64_t)cy * nx + cx);
+      } else if (oy && !ox && gy != nullptr) {
+        const T gv = (T)gy[(int64_t)zl * nx + cx];
         val = Tr::kReduced ? gv * d.inv_scale : gv;
       }
     }
     v[b] = val;
   }
-  T acc = d.tw[0] * v[0];
-#pragma unroll
-  for (int b = 1; b < 8; ++b) acc = fma(d.tw[b], v[b], acc);
-  if (Tr::kReduced) acc *= d.scale;
-  return acc;
+  own = v[0];
+  return interp4(d, v[0], v[1], v[2], v[3]);
 }
 
-// ---------------------------------------------------------------------------
-// Main-path helpers.  Lanes on an x face re-target the x-shifted taps to the
-// wrapped cell (periodic) or to their own cell (vacuum or inflow; the value is
-// replaced in main_interp), so every address stays in the box.
-// ---------------------------------------------------------------------------
-template <typename S>
-__device__ __forceinline__ void main_load(const DirTab<typename StoreTraits<S>::T> &d,
-                                          const char *base, uint32_t c0, bool at_lo, bool at_hi,
-                                          bool perx, int nx, typename StoreTraits<S>::T (&v)[8]) {
-  constexpr int SZ = (int)sizeof(S);
-  const char *P = base + d.plane_off;
-  const int s0 = d.s[0];
-  const bool bad = s0 > 0 ? at_lo : (s0 < 0 ? at_hi : false);
-  const int32_t adj = perx ? s0 * nx * SZ : s0 * SZ;
-  const uint32_t c1 = c0 + (bad ? (uint32_t)adj : 0u);
-#pragma unroll
-  for (int b = 0; b < 8; ++b) v[b] = ld_byte<S>(P, ((b & 1) ? c1 : c0) + (uint32_t)d.off[b]);
-}
-
+// Plane value of a plane outside the box in z (non-periodic): taps inside the
+// box in x and y read the z-face inflow ghost plane ([y][x] layout); all other
+// taps are vacuum.
 template <typename S>
 __device__ __forceinline__ typename StoreTraits<S>::T
-main_interp(const DirTab<typename StoreTraits<S>::T> &d, bool at_lo, bool at_hi, bool perx,
-            typename StoreTraits<S>::T (&v)[8]) {
+ghost_P(const DirTab<typename StoreTraits<S>::T> &d, const float *gz, int x, int y, bool valid,
+        int nx, int ny, int perx, int pery) {
   using Tr = StoreTraits<S>;
   using T = typename Tr::T;
-  // x-face lanes of non-periodic boxes: the x-shifted taps are ghosts; they
-  // enter here as vacuum (0) and inflow ghost values are added afterwards by
-  // x_ghost_correction
-  const int s0 = d.s[0];
-  const bool bad = !perx && (s0 > 0 ? at_lo : (s0 < 0 ? at_hi : false));
-  v[1] = bad ? T(0) : v[1];
-  v[3] = bad ? T(0) : v[3];
-  v[5] = bad ? T(0) : v[5];
-  v[7] = bad ? T(0) : v[7];
-  T acc = d.tw[0] * v[0];
+  if (gz == nullptr || !valid) return T(0);
+  T v[4];
 #pragma unroll
-  for (int b = 1; b < 8; ++b) acc = fma(d.tw[b], v[b], acc);
-  if (Tr::kReduced) acc *= d.scale;
-  return acc;
+  for (int b = 0; b < 4; ++b) {
+    int cx = x - (b & 1) * d.s[0];
+    int cy = y - (b >> 1) * d.s[1];
+    if (perx) cx = wrap(cx, nx);
+    if (pery) cy = wrap(cy, ny);
+    T val = T(0);
+    if ((unsigned)cx < (unsigned)nx && (unsigned)cy < (unsigned)ny) {
+      const T gv = (T)gz[(int64_t)cy * nx + cx];
+      val = Tr::kReduced ? gv * d.inv_scale : gv;
+    }
+    v[b] = val;
+  }
+  return interp4(d, v[0], v[1], v[2], v[3]);
 }
 
 // Inflow ghost values on an x face, for a lane on that face: the x-shifted
 // taps read the face's ghost plane ([z][y] layout).  Every path computes I*
-// with vacuum x ghosts first and adds this term, so all paths agree bit for bit.
-// A tap that also leaves the box along y or z (an edge ghost) stays vacuum.
+// with vacuum x ghosts first and adds this term, so all paths agree bit for
+// bit.  A tap that also leaves the box along y or z (an edge ghost) stays
+// vacuum.
 template <typename T>
-__device__ __forceinline__ T x_ghost_correction(const DirTab<T> &d, const float *gx, int y,
-                                                int z, int ny, int nz, int py, int pz) {
+__device__ __forceinline__ T x_ghost_correction(const DirTab<T> &d, const float *gx, int y, int z,
+                                                int ny, int nz, int py, int pz) {
   T acc = T(0);
 #pragma unroll
   for (int b = 1; b < 8; b += 2) {
     int cy = y - ((b >> 1) & 1) * d.s[1];
     int cz = z - (b >> 2) * d.s[2];
-    if (py) cy = cy < 0 ? cy + ny : (cy >= ny ? cy - ny : cy);
-    if (pz) cz = cz < 0 ? cz + nz : (cz >= nz ? cz - nz : cz);
+    if (py) cy = wrap(cy, ny);
+    if (pz) cz = wrap(cz, nz);
     if ((unsigned)cy < (unsigned)ny && (unsigned)cz < (unsigned)nz)
       acc = fma(d.tw[b], (T)gx[(int64_t)cz * ny + cy], acc);
   }
   return acc;
 }
 
+// Energy entering cell (x, y, z) from the inflow ghost plane g of a y or z
+// face (axis a = 1 or 2): the taps shifted along a, with the other two
+// coordinates inside the box (face layouts: y faces [z][x], z faces [y][x]).
+template <typename T>
+__device__ inline T ghost_influx(const DirTab<T> &d, const float *g, int a, int x, int y, int z,
+                                 int nx, int ny, int nz, const int *per) {
+  const int n3[3] = {nx, ny, nz};
+  const int c3[3] = {x, y, z};
+  const int o2 = a == 1 ? 2 : 1;   // the other non-x axis
+  T acc = T(0);
+  for (int b = 0; b < 8; ++b) {
+    if (((b >> a) & 1) == 0) continue;
+    int u = c3[0] - (b & 1) * d.s[0];
+    int w = c3[o2] - ((b >> o2) & 1) * d.s[o2];
+    if (per[0]) u = wrap(u, n3[0]);
+    if (per[o2]) w = wrap(w, n3[o2]);
+    if ((unsigned)u < (unsigned)n3[0] && (unsigned)w < (unsigned)n3[o2])
+      acc = fma(d.tw[b], (T)g[(int64_t)w * n3[0] + u], acc);
+  }
+  return acc;
+}
+
 // ---------------------------------------------------------------------------
-// Per-slot moment accumulation, done as soon as a streamed value exists so
-// that the interpolation of every slot completes in place (no long-lived taps).
+// Per-slot moment accumulation, done as soon as a streamed value exists.
 //   static fluid: E* and F*, slots taken in pairs (a, b):
 //       E += a + b,  F += n_a (a - b) + (n_a + n_b) b,
 //     exact F-cancellation for antipodal pairs (n_a + n_b = 0), plain sums
@@ -282,27 +327,18 @@ __device__ __forceinline__ void accumulate(Acc<T> &m, const DirTab<T> *__restric
   }
 }
 
-// Unrolled loop helper: calls f.template operator()<J>() for J = 0..N-1.
-template <int J, int N, typename F>
-__device__ __forceinline__ void unroll(F &f) {
-  if constexpr (J < N) {
-    f.template operator()<J>();
-    unroll<J + 1, N>(f);
-  }
-}
-
 // ---------------------------------------------------------------------------
 // The fused step.  NB direction slots (a multiple of 8, padded with null
 // directions); wave q owns slots [q NB/4, (q+1) NB/4).
 // ---------------------------------------------------------------------------
-template <typename S, int NB, bool MOVING>
-__global__ void __launch_bounds__(kBlock)
-step_kernel(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__ ka,
-            const float *__restrict__ ks, const float *__restrict__ eta,
-            const float *__restrict__ vel,
-            const DirTab<typename StoreTraits<S>::T> *__restrict__ tab, const KParams p,
-            const InflowArgs *__restrict__ inflow, typename StoreTraits<S>::T *__restrict__ Eout,
-            typename StoreTraits<S>::T *__restrict__ Fout, double *__restrict__ partials) {
+template <typename S, int NB, bool MOVING, bool MAIN>
+__device__ __forceinline__ void
+march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__ ka,
+      const float *__restrict__ ks, const float *__restrict__ eta, const float *__restrict__ vel,
+      const DirTab<typename StoreTraits<S>::T> *__restrict__ tab, const KParams &p,
+      const InflowArgs *__restrict__ inflow, typename StoreTraits<S>::T *__restrict__ Eout,
+      typename StoreTraits<S>::T *__restrict__ Fout, double *__restrict__ partials, int x0,
+      int y0, int zb, int ze) {
   using Tr = StoreTraits<S>;
   using T = typename Tr::T;
   constexpr int SZ = (int)sizeof(S);
@@ -310,240 +346,499 @@ step_kernel(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__rest
   static_assert(NB % (2 * kWaves) == 0, "direction slots must split into pairs per wave");
 
   const int nx = p.nx, ny = p.ny, nz = p.nz;
-  int tix, tiy, tiz;
-  sweep_tile(xcd_tile(blockIdx.x, p.ntiles), p.ntx, p.nty, p.ntz, p.slab, tix, tiy, tiz);
-  const int x0 = tix * p.tx, y0 = tiy * p.ty, z0 = tiz * p.tz;
+  const int64_t pc = (int64_t)nx * ny;   // cells per z-plane
   const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // direction quarter
   const int lane = threadIdx.x & 63;
-  const int lx = lane % p.tx;
-  const int ly = (lane / p.tx) % p.ty;
-  const int lz = lane / (p.tx * p.ty);
-  const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
-  const bool valid = x < nx && y < ny && z < nz;
-  const uint32_t cell = valid ? (uint32_t)(x + nx * (y + ny * z)) : 0u;
+  const int perx = p.periodic[0], pery = p.periodic[1], perz = p.periodic[2];
 
-  // Tiles whose y and z halos stay inside the box, with no ragged lanes, take
-  // the main path; its x faces are handled per lane.
-  const bool yz_inside = y0 >= 1 && z0 >= 1 && y0 + p.ty <= ny - 1 && z0 + p.tz <= nz - 1;
-  const bool full_x = x0 + p.tx <= nx;
-  const bool main_path = yz_inside && full_x;
+  const int x = x0 + (lane & (p.tx - 1));
+  const int y = y0 + (lane >> p.txlog);
+  const bool valid = x < nx && y < ny;
+  // Byte offsets in a plane: the lane's cell, and its x-shifted tap x - sx
+  // for sx > 0 / sx < 0; on a face lane the wrapped cell (periodic) or the
+  // lane's own cell (a vacuum/inflow ghost: zeroed).  All offsets stay inside
+  // the plane.
+  const uint32_t o0 = valid ? (uint32_t)(x + nx * y) * (uint32_t)SZ : 0u;
+  const bool at0 = valid && x == 0, at1 = valid && x == nx - 1;
+  uint32_t oxp = at0 ? (perx ? o0 + (uint32_t)((nx - 1) * SZ) : o0) : o0 - (uint32_t)SZ;
+  uint32_t oxm = at1 ? (perx ? o0 - (uint32_t)((nx - 1) * SZ) : o0) : o0 + (uint32_t)SZ;
+  if (!valid) oxp = oxm = 0u;
+  const bool lox = at0 && !perx, hix = at1 && !perx;   // on a non-periodic x face
+  const bool loy = valid && y == 0 && !pery, hiy = valid && y == ny - 1 && !pery;
+  // Main path, per lane: 1 where the x-shifted tap of a direction with
+  // sx > 0 / sx < 0 is a vacuum or inflow ghost (zeroed), and 1 where such a
+  // direction leaves through the lane's face (outflux weight).  A slot's
+  // factor is sum over the two signs of (slot's sign factor) * (lane value):
+  // plain FMAs with uniform operands, no per-slot lane masks.
+  const T xzp = lox ? T(1) : T(0), xzm = hix ? T(1) : T(0);
+  const T xop = hix ? T(1) : T(0), xom = lox ? T(1) : T(0);
 
+  const bool diag = (p.flags & KF_DIAG) != 0;
+  const bool xface_tile = !perx && (x0 == 0 || x0 + p.tx >= nx);
+  const bool face_tile = xface_tile || (!pery && (y0 == 0 || y0 + p.ty >= ny));
+
+  // This wave's slots.  The table holds two identical copies of the NB slots;
+  // plane z reads copy z & 1.  The table is thus re-read (scalar cache hits)
+  // on every plane instead of being hoisted out of the z loop, which would
+  // keep hundreds of uniform values live in SGPRs and spill them.
+  const DirTab<T> *__restrict__ tb = tab + q * M;
   const T dt = (T)p.dt;
-  T kat = T(0), kst = T(0), et = T(0);
-  T vx = T(0), vy = T(0), vz = T(0);
-  if (valid) {
-    kat = (T)ka[cell];
-    kst = (T)ks[cell];
-    et = (T)eta[cell];
-    if constexpr (MOVING) {
-      vx = (T)vel[cell];
-      vy = (T)vel[p.ncell + cell];
-      vz = (T)vel[2 * p.ncell + cell];
+
+  // Diagnostics, per lane: sums of E and E* (wave 0), outflux through the
+  // lane's x and y faces, influx (z faces: a separate kernel).
+  double sE = 0.0, sEs = 0.0, fin = 0.0;
+  T fx = T(0), fy = T(0);
+
+  // Plane value of slot d (processing slot index `slot`) at plane zl by the
+  // general rules: a plane outside the box in z is the z ghost plane (or
+  // vacuum), otherwise each tap is checked.  With `book` (zl is one of this
+  // block's planes) the own value is booked as x/y-face outflux.
+  auto general_P = [&](const DirTab<T> &d, int slot, int zl, bool book) -> T {
+    if ((unsigned)zl >= (unsigned)nz)
+      return ghost_P<S>(d, inflow->ghost[slot][2], x, y, valid, nx, ny, perx, pery);
+    T own;
+    const S *pl = Iin + (d.plane_off / SZ) + (int64_t)zl * pc;
+    const T P = checked_P<S>(d, pl, x, y, valid, nx, ny, perx, pery, inflow->ghost[slot][1], zl,
+                             own);
+    if (diag && book && face_tile && valid) {
+      T fz = T(0);
+      book_outflux(d, Tr::kReduced ? own * d.scale : own, lox, hix, loy, hiy, false, false, fx, fy,
+                   fz, fz);
     }
-  }
-  T W = T(1), dtWk = T(0);
-  if constexpr (MOVING) {
-    W = T(1) / sqrt(T(1) - (vx * vx + vy * vy + vz * vz));
-    dtWk = dt * W * (kat + kst);
-  }
-
-  const DirTab<T> *__restrict__ tb = tab + q * M;   // this wave's slots
-  T Is[M];
-  Acc<T> m;
-
-  if (main_path) {
-    const char *base = reinterpret_cast<const char *>(Iin);
-    const uint32_t c0 = cell * (uint32_t)SZ;
-    const bool at_lo = x == 0, at_hi = x == nx - 1;
-    const bool perx = p.periodic[0] != 0;
-    T cur[8];
-    main_load<S>(tb[0], base, c0, at_lo, at_hi, perx, nx, cur);
-    // each slot prefetches the next slot's taps before interpolating its own
-    auto body = [&]<int J>() {
-      T nxt[8];
-      if constexpr (J + 1 < M) main_load<S>(tb[J + 1], base, c0, at_lo, at_hi, perx, nx, nxt);
-      Is[J] = main_interp<S>(tb[J], at_lo, at_hi, perx, cur);
-      accumulate<MOVING, J>(m, tb, Is, vx, vy, vz, dtWk);
-      if constexpr (J + 1 < M) {
-#pragma unroll
-        for (int b = 0; b < 8; ++b) cur[b] = nxt[b];
-      }
-    };
-    unroll<0, M>(body);
-  } else {
-    const int px = p.periodic[0], py = p.periodic[1], pz = p.periodic[2];
-    auto body = [&]<int J>() {
-      const DirTab<T> &d = tb[J];
-      T acc = T(0);
-      if (valid) {
-        const S *P = Iin + (int64_t)d.plane * p.ncell;
-        const float *const *g = inflow->ghost[q * M + J];
-        // x-face inflow ghosts come in through x_ghost_correction below
-        acc = stream_checked<S>(P, d, x, y, z, nx, ny, nz, px, py, pz, nullptr, g[1], g[2]);
-      }
-      Is[J] = acc;
-      accumulate<MOVING, J>(m, tb, Is, vx, vy, vz, dtWk);
-    };
-    unroll<0, M>(body);
-  }
-  if (p.flags & KF_XGHOSTS) {
-    // Inflow ghosts on the x faces enter after the vacuum sums, slot by slot,
-    // for the face lanes of the directions that have a ghost plane there.
-    const bool xlo = valid && x == 0 && !p.periodic[0];
-    const bool xhi = valid && x == nx - 1 && !p.periodic[0];
-    auto body = [&]<int J>() {
-      const DirTab<T> &d = tb[J];
-      const float *gx = inflow->ghost[q * M + J][0];
-      if (gx != nullptr && (d.s[0] > 0 ? xlo : (d.s[0] < 0 ? xhi : false))) {
-        T dI = x_ghost_correction<T>(d, gx, y, z, ny, nz, p.periodic[1], p.periodic[2]);
-        Is[J] += dI;
-        m.Es += dI;
-        if constexpr (MOVING) {
-          const T D = T(1) - (vx * d.n[0] + vy * d.n[1] + vz * d.n[2]);
-          const T a = rcp<T>(fma(dtWk, D, T(1)));
-          m.F0 = fma(D * D * a, dI, m.F0);
-        } else {
-          m.F0 = fma(d.n[0], dI, m.F0);
-          m.F1 = fma(d.n[1], dI, m.F1);
-          m.F2 = fma(d.n[2], dI, m.F2);
-        }
-      }
-    };
-    unroll<0, M>(body);
-  }
-
-  // Combine the four waves' partial sums in a fixed order,
-  // (q0 + q1) + (q2 + q3), identical in every wave.
-  __shared__ T red[kWaves][4][64];
-  red[q][0][lane] = m.Es;
-  red[q][1][lane] = m.F0;
-  red[q][2][lane] = m.F1;
-  red[q][3][lane] = m.F2;
-  __syncthreads();
-  auto comb = [&](int j) {
-    return (red[0][j][lane] + red[1][j][lane]) + (red[2][j][lane] + red[3][j][lane]);
+    return P;
   };
-  const T Es = comb(0), S0 = comb(1), S1 = comb(2), S2 = comb(3);
+  // Main-path loads of the four taps of slot d from the plane whose element
+  // offset (z * pc) is cz: rows y and y - sy, each unshifted and x-shifted.
+  // The x-shifted offset is o0 plus the lane's delta for the slot's sign of
+  // sx, selected with the slot's all-ones/zero masks.
+  const uint32_t dxp = oxp - o0, dxm = oxm - o0;
+  auto load4 = [&](const DirTab<T> &d, int64_t cz, T (&v)[4]) {
+    const S *r0 = Iin + d.plane_el + cz;
+    const S *r1 = r0 + d.row_shift;
+    const uint32_t a0 = o0;
+    const uint32_t ax = a0 + (dxp & d.mxp) + (dxm & d.mxm);
+    v[0] = ldo<S>(r0, a0);
+    v[1] = ldo<S>(r0, ax);
+    v[2] = ldo<S>(r1, a0);
+    v[3] = ldo<S>(r1, ax);
+  };
+  // factor of the x-shifted taps of slot d for this lane (0 at a ghost)
+  auto xkeep = [&](const DirTab<T> &d) {
+    return fma(-d.cxp, xzp, fma(-d.cxm, xzm, T(1)));
+  };
+  // The new plane of a slot at output plane z (wrapped on a periodic z axis;
+  // outside [0, nz) it is a z ghost plane), and whether it is one of this
+  // block's own planes (own values are booked as outflux exactly once).
+  auto new_plane = [&](const DirTab<T> &d, int z) {
+    int zl = z + (d.s[2] < 0 ? 1 : 0);
+    if (perz) zl = wrap(zl, nz);
+    return zl;
+  };
+  auto own_plane = [&](const DirTab<T> &d, int z) { return d.s[2] >= 0 || z + 1 < ze; };
 
-  T En = T(0), Fn0 = T(0), Fn1 = T(0), Fn2 = T(0);
-  if constexpr (!MOVING) {
-    const T F0 = S0, F1 = S1, F2 = S2;
-    // Collision: every mode becomes I_i = c I*_i + w_i (alpha + n_i . beta).
-    const T lam = (T)p.lam;
-    T c, alpha, be0, be1, be2;
-    if (p.mode == LBRT_COLL_EXPLICIT) {
-      // eq. (collision-step) with I^eq and S of eq. (source-and-equil)
-      c = T(1) - dt * (kst + kat);
-      alpha = dt * (kst * Es + et);
-      const T g = dt * kst * lam;
-      be0 = g * F0; be1 = g * F1; be2 = g * F2;
-      En = c * Es + alpha;
-      Fn0 = c * F0 + be0 / T(3); Fn1 = c * F1 + be1 / T(3); Fn2 = c * F2 + be2 / T(3);
-    } else if (p.mode == LBRT_COLL_LAMBDA) {
-      // Lambda iteration: (E, F) <- moments of the decoupled solution, which
-      // the rule's identities reduce to a scalar recursion per cell.
-      c = T(1) / (T(1) + dt * (kst + kat));
-      T Ek = Es, G0 = F0, G1 = F1, G2 = F2;
-      const T h = dt * kst * lam / T(3);
-      for (int it = 1; it < p.lambda_iters; ++it) {
-        Ek = c * (Es + dt * (kst * Ek + et));
-        G0 = c * (F0 + h * G0); G1 = c * (F1 + h * G1); G2 = c * (F2 + h * G2);
+  // Prologue: the carried plane of every slot (P at zb - 1 for sz > 0, at zb
+  // for sz < 0; nothing for sz == 0).  On the main path a plane outside the
+  // box is vacuum (its clamped loads are weighted by 0).
+  T carry[M];
+  {
+    auto pro = [&]<int J>() {
+      const DirTab<T> &d = tb[J];
+      carry[J] = T(0);
+      if (d.s[2] != 0) {
+        int zl = d.s[2] > 0 ? zb - 1 : zb;
+        if (perz) zl = wrap(zl, nz);
+        if constexpr (MAIN) {
+          T v[4];
+          const bool in = (unsigned)zl < (unsigned)nz;
+          load4(d, (int64_t)min(max(zl, 0), nz - 1) * pc, v);
+          const T k1 = xkeep(d);
+          carry[J] = (in ? T(1) : T(0)) * interp4(d, v[0], v[1] * k1, v[2], v[3] * k1);
+          if (diag && d.s[2] < 0) fx = fma(fma(d.cxp, xop, d.cxm * xom) * d.dxs, v[0], fx);
+        } else {
+          carry[J] = general_P(d, q * M + J, zl, d.s[2] < 0);
+        }
       }
-      alpha = c * dt * (kst * Ek + et);
-      const T g = c * dt * kst * lam;
-      be0 = g * G0; be1 = g * G1; be2 = g * G2;
-      En = c * Es + alpha;
-      Fn0 = c * F0 + be0 / T(3); Fn1 = c * F1 + be1 / T(3); Fn2 = c * F2 + be2 / T(3);
+    };
+    unroll<0, M>(pro);
+  }
+
+  __shared__ T red[2][kWaves][4][64];
+  T cur[4] = {T(0), T(0), T(0), T(0)};
+  // element offsets of the new planes of output plane z: z (sz >= 0) and the
+  // plane above (sz < 0), clamped into the box on a non-periodic axis
+  auto plane_above = [&](int z) {
+    const int za = z + 1 < nz ? z + 1 : (perz ? 0 : nz - 1);
+    return (int64_t)za * pc;
+  };
+  if constexpr (MAIN)
+    if (zb < ze) load4(tb[0], tb[0].dzn ? plane_above(zb) : (int64_t)zb * pc, cur);
+
+  for (int z = zb; z < ze; ++z) {
+    const int par = (z - zb) & 1;
+    tb = tab + (z & 1) * NB + q * M;
+    const int64_t cz = (int64_t)z * pc;
+    const int64_t cell = cz + (int64_t)(o0 / (uint32_t)SZ);
+
+    T kat = T(0), kst = T(0), et = T(0);
+    T vx = T(0), vy = T(0), vz = T(0);
+    if (valid) {
+      kat = (T)ka[cell];
+      kst = (T)ks[cell];
+      et = (T)eta[cell];
+      if constexpr (MOVING) {
+        vx = (T)vel[cell];
+        vy = (T)vel[p.ncell + cell];
+        vz = (T)vel[2 * p.ncell + cell];
+      }
+    }
+    T W = T(1), dtWk = T(0);
+    if constexpr (MOVING) {
+      W = T(1) / sqrt(T(1) - (vx * vx + vy * vy + vz * vz));
+      dtWk = dt * W * (kat + kst);
+    }
+
+    T Is[M];
+    Acc<T> m;
+    if constexpr (MAIN) {
+      // Each slot issues the next slot's loads before interpolating its own.
+      // A new plane above the box (sz < 0 on the last plane of a
+      // non-periodic z axis) is vacuum: its clamped loads get weight 0.
+      const int64_t cz1 = plane_above(z);
+      // the plane above a non-periodic box is vacuum: weight 0
+      const bool top_ghost = !perz && z + 1 >= nz;
+      // BOOK: also book the x-face outflux of the own values (x-face tiles
+      // with diagnostics on; a block-uniform choice between two copies of
+      // the slot loop keeps the common one free of branches)
+      auto slot = [&]<int J, bool BOOK>() {
+        const DirTab<T> &d = tb[J];
+        T nxt[4];
+        if constexpr (J + 1 < M) load4(tb[J + 1], tb[J + 1].dzn ? cz1 : cz, nxt);
+        const T k1 = xkeep(d);
+        const T Pn = interp4(d, cur[0], cur[1] * k1, cur[2], cur[3] * k1);
+        if constexpr (BOOK) {
+          // the plane above the range belongs to the next block
+          const T ko = fma(d.cxp, xop, d.cxm * xom);
+          const T dxs = (d.dzn && z + 1 >= ze) ? T(0) : d.dxs;
+          fx = fma(ko * dxs, cur[0], fx);
+        }
+        const T wn = (d.dzn && top_ghost) ? T(0) : d.wz_new;
+        T sv = fma(d.wz_old, carry[J], wn * Pn);
+        if (Tr::kReduced) sv *= d.scale;
+        Is[J] = sv;
+        carry[J] = Pn;
+        accumulate<MOVING, J>(m, tb, Is, vx, vy, vz, dtWk);
+        if constexpr (J + 1 < M) {
+#pragma unroll
+          for (int b = 0; b < 4; ++b) cur[b] = nxt[b];
+        }
+      };
+      auto body_book = [&]<int J>() { slot.template operator()<J, true>(); };
+      auto body = [&]<int J>() { slot.template operator()<J, false>(); };
+      if (diag && xface_tile)
+        unroll<0, M>(body_book);
+      else
+        unroll<0, M>(body);
     } else {
-      // eq. (rte_implicit) solved exactly: the moment equations decouple to
-      // E = (E* + dt eta)/(1 + dt ka), F = F*/(1 + dt(k0 + ka) - dt k0 lam/3).
-      const T den = T(1) + dt * (kst + kat);
-      c = T(1) / den;
-      En = (Es + dt * et) / (T(1) + dt * kat);
-      const T gF = T(1) / (den - dt * kst * lam / T(3));
-      Fn0 = F0 * gF; Fn1 = F1 * gF; Fn2 = F2 * gF;
-      alpha = c * dt * (kst * En + et);
-      const T g = c * dt * kst * lam;
-      be0 = g * Fn0; be1 = g * Fn1; be2 = g * Fn2;
+      auto body = [&]<int J>() {
+        const DirTab<T> &d = tb[J];
+        const T Pn = general_P(d, q * M + J, new_plane(d, z), own_plane(d, z));
+        T sv = fma(d.wz_old, carry[J], d.wz_new * Pn);
+        if (Tr::kReduced) sv *= d.scale;
+        Is[J] = valid ? sv : T(0);
+        carry[J] = Pn;
+        accumulate<MOVING, J>(m, tb, Is, vx, vy, vz, dtWk);
+      };
+      unroll<0, M>(body);
     }
-    if (valid) {
-      if (p.flags & KF_LAMZERO) {
-#pragma unroll
-        for (int j = 0; j < M; ++j) {
-          if (q * M + j < p.ndir) {
-            const DirTab<T> &d = tb[j];
-            T o = fma(c, Is[j], d.w * alpha);
-            if (Tr::kReduced) o *= d.inv_scale;
-            Tr::st(Iout + (int64_t)d.plane * p.ncell + cell, o);
+    if (p.flags & KF_XGHOSTS) {
+      // Inflow ghosts on the x faces enter after the vacuum sums, slot by
+      // slot, for the face lanes of the directions with a ghost plane there.
+      auto body = [&]<int J>() {
+        const DirTab<T> &d = tb[J];
+        const float *gx = inflow->ghost[q * M + J][0];
+        if (gx != nullptr && (d.s[0] > 0 ? lox : (d.s[0] < 0 ? hix : false))) {
+          const T dI = x_ghost_correction<T>(d, gx, y, z, ny, nz, pery, perz);
+          fin += (double)dI;
+          Is[J] += dI;
+          m.Es += dI;
+          if constexpr (MOVING) {
+            const T D = T(1) - (vx * d.n[0] + vy * d.n[1] + vz * d.n[2]);
+            const T a = rcp<T>(fma(dtWk, D, T(1)));
+            m.F0 = fma(D * D * a, dI, m.F0);
+          } else {
+            m.F0 = fma(d.n[0], dI, m.F0);
+            m.F1 = fma(d.n[1], dI, m.F1);
+            m.F2 = fma(d.n[2], dI, m.F2);
           }
         }
-      } else {
-#pragma unroll
-        for (int j = 0; j < M; ++j) {
-          if (q * M + j < p.ndir) {
-            const DirTab<T> &d = tb[j];
-            const T nb = alpha + d.n[0] * be0 + d.n[1] * be1 + d.n[2] * be2;
-            T o = fma(c, Is[j], d.w * nb);
-            if (Tr::kReduced) o *= d.inv_scale;
-            Tr::st(Iout + (int64_t)d.plane * p.ncell + cell, o);
-          }
-        }
-      }
+      };
+      unroll<0, M>(body);
     }
-  } else {
-    // Mixed-frame implicit collision (App. B): with D_i = 1 - v.n_i,
-    // a_i = 1/(1 + dt W D_i (ka + k0)) and J = W^2 sum_i D_i^2 I_i (eq. J),
-    //   J = (A + eta B) / (1 - k0 B),  A = W^2 sum D_i^2 a_i I*_i,
-    //   B = (dt/W) sum w_i a_i / D_i,
-    //   I_i = a_i [I*_i + dt w_i (eta + k0 J) / (W^3 D_i^3)].
-    const T A = S0 * (W * W);
-    const T B = S1 * (dt / W);
-    const T J = (A + et * B) / (T(1) - kst * B);
-    const T gam = dt * (et + kst * J) / (W * W * W);
-    T e = T(0), f0 = T(0), f1 = T(0), f2 = T(0);
-    if (valid) {
-#pragma unroll
+    if (!MAIN && diag && (loy || hiy)) {
+      // influx from inflow ghost planes on the y faces (a runtime loop)
       for (int j = 0; j < M; ++j) {
-        if (q * M + j < p.ndir) {
-          const DirTab<T> &d = tb[j];
-          const T D = T(1) - (vx * d.n[0] + vy * d.n[1] + vz * d.n[2]);
-          const T a = rcp<T>(fma(dtWk, D, T(1)));
-          const T iD = rcp<T>(D);
-          const T o = a * fma(d.w * gam, iD * iD * iD, Is[j]);
-          e += o;
-          f0 = fma(d.n[0], o, f0);
-          f1 = fma(d.n[1], o, f1);
-          f2 = fma(d.n[2], o, f2);
-          Tr::st(Iout + (int64_t)d.plane * p.ncell + cell, Tr::kReduced ? o * d.inv_scale : o);
-        }
+        const DirTab<T> &d = tb[j];
+        const float *g = inflow->ghost[q * M + j][1];
+        const bool on = d.s[1] > 0 ? loy : (d.s[1] < 0 ? hiy : false);
+        if (g != nullptr && on)
+          fin += (double)ghost_influx<T>(d, g, 1, x, y, z, nx, ny, nz, p.periodic);
       }
     }
-    // moments of the new state, combined like the streamed ones
+
+    // Combine the four waves' partial sums in a fixed order,
+    // (q0 + q1) + (q2 + q3), identical in every wave.
+    red[par][q][0][lane] = m.Es;
+    red[par][q][1][lane] = m.F0;
+    red[par][q][2][lane] = m.F1;
+    red[par][q][3][lane] = m.F2;
     __syncthreads();
-    red[q][0][lane] = e;
-    red[q][1][lane] = f0;
-    red[q][2][lane] = f1;
-    red[q][3][lane] = f2;
-    __syncthreads();
-    En = comb(0); Fn0 = comb(1); Fn1 = comb(2); Fn2 = comb(3);
+    auto comb = [&](int b, int j) {
+      return (red[b][0][j][lane] + red[b][1][j][lane]) + (red[b][2][j][lane] + red[b][3][j][lane]);
+    };
+    const T Es = comb(par, 0), S0 = comb(par, 1), S1 = comb(par, 2), S2 = comb(par, 3);
+
+    // the next plane's first loads go out before the collision's stores
+    if constexpr (MAIN)
+      if (z + 1 < ze) load4(tb[0], tb[0].dzn ? plane_above(z + 1) : cz + pc, cur);
+
+    S *const outz = Iout + cz;
+    // The collision reads the other copy of the table, so that its loads are
+    // not merged with the streaming phase's (which would keep those values
+    // live across the barrier).
+    const DirTab<T> *__restrict__ tbc = tab + ((z & 1) ^ 1) * NB + q * M;
+    T En = T(0), Fn0 = T(0), Fn1 = T(0), Fn2 = T(0);
+    if constexpr (!MOVING) {
+      const T F0 = S0, F1 = S1, F2 = S2;
+      // Collision: every mode becomes I_i = c I*_i + w_i (alpha + n_i . beta).
+      const T lam = (T)p.lam;
+      T c, alpha, be0, be1, be2;
+      if (p.mode == LBRT_COLL_EXPLICIT) {
+        // eq. (collision-step) with I^eq and S of eq. (source-and-equil)
+        c = T(1) - dt * (kst + kat);
+        alpha = dt * (kst * Es + et);
+        const T g = dt * kst * lam;
+        be0 = g * F0; be1 = g * F1; be2 = g * F2;
+        En = c * Es + alpha;
+        Fn0 = c * F0 + be0 / T(3); Fn1 = c * F1 + be1 / T(3); Fn2 = c * F2 + be2 / T(3);
+      } else if (p.mode == LBRT_COLL_LAMBDA) {
+        // Lambda iteration: (E, F) <- moments of the decoupled solution,
+        // which the rule's identities reduce to a scalar recursion per cell.
+        c = T(1) / (T(1) + dt * (kst + kat));
+        T Ek = Es, G0 = F0, G1 = F1, G2 = F2;
+        const T h = dt * kst * lam / T(3);
+        for (int it = 1; it < p.lambda_iters; ++it) {
+          Ek = c * (Es + dt * (kst * Ek + et));
+          G0 = c * (F0 + h * G0); G1 = c * (F1 + h * G1); G2 = c * (F2 + h * G2);
+        }
+        alpha = c * dt * (kst * Ek + et);
+        const T g = c * dt * kst * lam;
+        be0 = g * G0; be1 = g * G1; be2 = g * G2;
+        En = c * Es + alpha;
+        Fn0 = c * F0 + be0 / T(3); Fn1 = c * F1 + be1 / T(3); Fn2 = c * F2 + be2 / T(3);
+      } else {
+        // eq. (rte_implicit) solved exactly: the moment equations decouple to
+        // E = (E* + dt eta)/(1 + dt ka), F = F*/(1 + dt(k0 + ka) - dt k0 lam/3).
+        const T den = T(1) + dt * (kst + kat);
+        c = T(1) / den;
+        En = (Es + dt * et) / (T(1) + dt * kat);
+        const T gF = T(1) / (den - dt * kst * lam / T(3));
+        Fn0 = F0 * gF; Fn1 = F1 * gF; Fn2 = F2 * gF;
+        alpha = c * dt * (kst * En + et);
+        const T g = c * dt * kst * lam;
+        be0 = g * Fn0; be1 = g * Fn1; be2 = g * Fn2;
+      }
+      if (valid) {
+        if (p.flags & KF_LAMZERO) {
+#pragma unroll
+          for (int j = 0; j < M; ++j) {
+            const DirTab<T> &d = tbc[j];
+            if (d.active) {
+              T o = fma(c, Is[j], d.w * alpha);
+              if (Tr::kReduced) o *= d.inv_scale;
+              Tr::st(reinterpret_cast<S *>(reinterpret_cast<char *>(outz + d.plane_off / SZ) +
+                                           o0), o);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < M; ++j) {
+            const DirTab<T> &d = tbc[j];
+            if (d.active) {
+              const T nb = alpha + d.n[0] * be0 + d.n[1] * be1 + d.n[2] * be2;
+              T o = fma(c, Is[j], d.w * nb);
+              if (Tr::kReduced) o *= d.inv_scale;
+              Tr::st(reinterpret_cast<S *>(reinterpret_cast<char *>(outz + d.plane_off / SZ) +
+                                           o0), o);
+            }
+          }
+        }
+      }
+    } else {
+      // Mixed-frame implicit collision (App. B): with D_i = 1 - v.n_i,
+      // a_i = 1/(1 + dt W D_i (ka + k0)) and J = W^2 sum_i D_i^2 I_i (eq. J),
+      //   J = (A + eta B) / (1 - k0 B),  A = W^2 sum D_i^2 a_i I*_i,
+      //   B = (dt/W) sum w_i a_i / D_i,
+      //   I_i = a_i [I*_i + dt w_i (eta + k0 J) / (W^3 D_i^3)].
+      const T A = S0 * (W * W);
+      const T B = S1 * (dt / W);
+      const T J = (A + et * B) / (T(1) - kst * B);
+      const T gam = dt * (et + kst * J) / (W * W * W);
+      T e = T(0), f0 = T(0), f1 = T(0), f2 = T(0);
+      if (valid) {
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+          const DirTab<T> &d = tbc[j];
+          if (d.active) {
+            const T D = T(1) - (vx * d.n[0] + vy * d.n[1] + vz * d.n[2]);
+            const T a = rcp<T>(fma(dtWk, D, T(1)));
+            const T iD = rcp<T>(D);
+            const T o = a * fma(d.w * gam, iD * iD * iD, Is[j]);
+            e += o;
+            f0 = fma(d.n[0], o, f0);
+            f1 = fma(d.n[1], o, f1);
+            f2 = fma(d.n[2], o, f2);
+            Tr::st(reinterpret_cast<S *>(reinterpret_cast<char *>(outz + d.plane_off / SZ) +
+                                         o0),
+                   Tr::kReduced ? o * d.inv_scale : o);
+          }
+        }
+      }
+      // Moments of the new state, combined like the streamed ones through the
+      // other half of the double buffer.  It is free: its last readers were
+      // the previous plane's, and every wave has passed this plane's barrier.
+      red[par ^ 1][q][0][lane] = e;
+      red[par ^ 1][q][1][lane] = f0;
+      red[par ^ 1][q][2][lane] = f1;
+      red[par ^ 1][q][3][lane] = f2;
+      __syncthreads();
+      En = comb(par ^ 1, 0);
+      Fn0 = comb(par ^ 1, 1);
+      Fn1 = comb(par ^ 1, 2);
+      Fn2 = comb(par ^ 1, 3);
+      // The next plane writes red[par ^ 1] only after every wave has read it.
+      __syncthreads();
+    }
+
+    if (q == 0 && valid) {
+      if (p.flags & KF_WRITE_EF) {
+        if (Eout) Eout[cell] = En;
+        if (Fout) {
+          Fout[cell] = Fn0;
+          Fout[p.ncell + cell] = Fn1;
+          Fout[2 * p.ncell + cell] = Fn2;
+        }
+      }
+      if (diag) {
+        sE += (double)En;
+        sEs += (double)Es;
+      }
+    }
   }
 
-  if (q == 0) {
-    if (valid && (p.flags & KF_WRITE_EF)) {
-      if (Eout) Eout[cell] = En;
-      if (Fout) {
-        Fout[cell] = Fn0;
-        Fout[p.ncell + cell] = Fn1;
-        Fout[2 * p.ncell + cell] = Fn2;
-      }
-    }
-  }
-  if (p.flags & KF_DIAG) {
+  if (diag) {
+    // per-block partials: sum E, sum E*, outflux per face (-x,+x,-y,+y,-z,+z),
+    // influx
     double v[kStepPartials];
-    v[0] = (valid && q == 0) ? (double)En : 0.0;
-    v[1] = (valid && q == 0) ? (double)Es : 0.0;
+    v[0] = sE;
+    v[1] = sEs;
+    v[2] = lox ? (double)fx : 0.0;
+    v[3] = hix ? (double)fx : 0.0;
+    v[4] = loy ? (double)fy : 0.0;
+    v[5] = hiy ? (double)fy : 0.0;
+    v[6] = 0.0;
+    v[7] = 0.0;
+    v[8] = fin;
     block_sums<kStepPartials>(v, partials + (int64_t)blockIdx.x * kStepPartials);
   }
+}
+
+// The main kernel: tiles whose y halo stays inside the box, with no ragged
+// lanes, in z ranges whose z ghost planes (if any) are vacuum.  Block id ->
+// tile in the XCD-aware order of xcd_tile.
+template <typename S, int NB, bool MOVING>
+__global__ void __launch_bounds__(kBlock)
+step_kernel_main(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__ ka,
+                 const float *__restrict__ ks, const float *__restrict__ eta,
+                 const float *__restrict__ vel,
+                 const DirTab<typename StoreTraits<S>::T> *__restrict__ tab, const KParams p,
+                 const InflowArgs *__restrict__ inflow,
+                 typename StoreTraits<S>::T *__restrict__ Eout,
+                 typename StoreTraits<S>::T *__restrict__ Fout, double *__restrict__ partials) {
+  const int t = xcd_tile(blockIdx.x, p.nblocks);
+  const int tix = t % p.ntx;
+  const int r = t / p.ntx;
+  const int tiy = p.main_ty0 + r % p.main_nty;
+  const int tzr = p.main_zr0 + r / p.main_nty;
+  const int zb = tzr * p.zlen;
+  march<S, NB, MOVING, true>(Iin, Iout, ka, ks, eta, vel, tab, p, inflow, Eout, Fout, partials,
+                             tix * p.tx, tiy * p.ty, zb, min(p.nz, zb + p.zlen));
+}
+
+// The general kernel: every other tile (y-face rows, ragged tiles, z ranges
+// next to an inflow z face), in short z ranges, from a host-built list of
+// (x0, y0, zb, ze).  Its partials follow the main kernel's.
+template <typename S, int NB, bool MOVING>
+__global__ void __launch_bounds__(kBlock)
+step_kernel_general(const S *__restrict__ Iin, S *__restrict__ Iout,
+                    const float *__restrict__ ka, const float *__restrict__ ks,
+                    const float *__restrict__ eta, const float *__restrict__ vel,
+                    const DirTab<typename StoreTraits<S>::T> *__restrict__ tab, const KParams p,
+                    const InflowArgs *__restrict__ inflow,
+                    typename StoreTraits<S>::T *__restrict__ Eout,
+                    typename StoreTraits<S>::T *__restrict__ Fout, double *__restrict__ partials) {
+  const int4 w = p.general_list[blockIdx.x];
+  march<S, NB, MOVING, false>(Iin, Iout, ka, ks, eta, vel, tab, p, inflow, Eout, Fout,
+                              partials + (int64_t)p.nblocks * kStepPartials, w.x, w.y, w.z, w.w);
+}
+
+// ---------------------------------------------------------------------------
+// Boundary energy fluxes through the z faces of the state entering a step
+// (non-periodic z only), as per-block partials in the step kernel's format
+// (columns 6 and 7: outflux through -z and +z; column 8: influx from z-face
+// inflow ghost planes).  One thread per cell of the two face planes; the
+// outflux of a cell that also lies on an x or y face is booked by the same
+// rule as in the step kernel (the x and y parts there, the rest here).
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ void __launch_bounds__(kBlock)
+zface_kernel(const S *__restrict__ I, const DirTab<typename StoreTraits<S>::T> *__restrict__ tab,
+             const KParams p, const InflowArgs *__restrict__ inflow,
+             double *__restrict__ partials) {
+  using Tr = StoreTraits<S>;
+  using T = typename Tr::T;
+  const int nx = p.nx, ny = p.ny, nz = p.nz;
+  const int64_t pc = (int64_t)nx * ny;
+  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;   // over 2 pc
+  double v[kStepPartials];
+#pragma unroll
+  for (int j = 0; j < kStepPartials; ++j) v[j] = 0.0;
+  if (k < 2 * pc) {
+    const int face = k >= pc;   // 0: z = 0, 1: z = nz - 1
+    const int64_t c = face ? k - pc : k;
+    const int y = (int)(c / nx), x = (int)(c - (int64_t)y * nx);
+    const int z = face ? nz - 1 : 0;
+    const bool lox = !p.periodic[0] && x == 0, hix = !p.periodic[0] && x == nx - 1;
+    const bool loy = !p.periodic[1] && y == 0, hiy = !p.periodic[1] && y == ny - 1;
+    T out = T(0), in = T(0);
+    for (int i = 0; i < p.ndir; ++i) {
+      const DirTab<T> &d = tab[i];
+      const int sz = d.s[2];
+      if (sz != 0 && (sz > 0) == (face == 1)) {
+        // leaves through this face
+        T own = Tr::ld(I + (d.plane_off / (int64_t)sizeof(S)) + (int64_t)z * pc + c);
+        if (Tr::kReduced) own *= d.scale;
+        T fx = T(0), fy = T(0), flo = T(0), fhi = T(0);
+        book_outflux(d, own, lox, hix, loy, hiy, face == 0, face == 1, fx, fy, flo, fhi);
+        out += flo + fhi;
+      }
+      const float *g = inflow->ghost[i][2];
+      if (g != nullptr && sz != 0 && (sz > 0) == (face == 0))
+        in += ghost_influx<T>(d, g, 2, x, y, z, nx, ny, nz, p.periodic);
+    }
+    v[6 + face] = (double)out;
+    v[8] = (double)in;
+  }
+  block_sums<kStepPartials>(v, partials + (int64_t)blockIdx.x * kStepPartials);
 }
 
 template <typename S, int NB, bool MOVING>
@@ -552,10 +847,17 @@ hipError_t launch_step(const void *Iin, void *Iout, const float *ka, const float
                        const InflowArgs *inflow, void *E, void *F, double *partials,
                        hipStream_t s) {
   using T = typename StoreTraits<S>::T;
-  hipLaunchKernelGGL((step_kernel<S, NB, MOVING>), dim3(p.ntiles), dim3(kBlock), 0, s,
-                     static_cast<const S *>(Iin), static_cast<S *>(Iout), ka, ks, eta, vel,
-                     static_cast<const DirTab<T> *>(tab), p, inflow, static_cast<T *>(E),
-                     static_cast<T *>(F), partials);
+  // the general kernel first: its short blocks do not leave a tail
+  if (p.ngeneral > 0)
+    hipLaunchKernelGGL((step_kernel_general<S, NB, MOVING>), dim3(p.ngeneral), dim3(kBlock), 0,
+                       s, static_cast<const S *>(Iin), static_cast<S *>(Iout), ka, ks, eta, vel,
+                       static_cast<const DirTab<T> *>(tab), p, inflow, static_cast<T *>(E),
+                       static_cast<T *>(F), partials);
+  if (p.nblocks > 0)
+    hipLaunchKernelGGL((step_kernel_main<S, NB, MOVING>), dim3(p.nblocks), dim3(kBlock), 0, s,
+                       static_cast<const S *>(Iin), static_cast<S *>(Iout), ka, ks, eta, vel,
+                       static_cast<const DirTab<T> *>(tab), p, inflow, static_cast<T *>(E),
+                       static_cast<T *>(F), partials);
   return hipGetLastError();
 }
 

@@ -52,9 +52,11 @@ def upload_fields(prob):
 
 
 def run_problem(prob, storage=None, steps=None, I0=None, want_diag=True, collision=None,
-                tile=None):
+                tile=None, zlen=None, zlen_general=None):
     """Run ``steps`` GPU steps; returns dict with float64 numpy I (decoded),
-    E, F, diag and the oracle's starting state ``I0_eff``."""
+    E, F, diag and the oracle's starting state ``I0_eff``.  ``tile``
+    ("TXxTY"), ``zlen`` and ``zlen_general`` override the context's tiling
+    (they change which cells take which kernel path, never the results)."""
     import os
     torch = torch_mod()
     L = lib()
@@ -64,17 +66,19 @@ def run_problem(prob, storage=None, steps=None, I0=None, want_diag=True, collisi
     if collision is not None:
         kw["collision"] = collision
     desc = L.Desc.from_problem(prob, storage=storage, **kw)
-    old = os.environ.get("LBRT_TILE")
-    if tile is not None:
-        os.environ["LBRT_TILE"] = tile
+    env = {"LBRT_TILE": tile, "LBRT_ZLEN": zlen, "LBRT_ZLEN_GENERAL": zlen_general}
+    old = {k: os.environ.get(k) for k in env}
+    for k, v in env.items():
+        if v is not None:
+            os.environ[k] = str(v)
     try:
         ctx = L.lbrt_init(desc)
     finally:
-        if tile is not None:
-            if old is None:
-                del os.environ["LBRT_TILE"]
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
             else:
-                os.environ["LBRT_TILE"] = old
+                os.environ[k] = v
     start = prob.I0 if I0 is None else I0
     Ia, I0_eff = host_encoded_state(np.asarray(start).reshape(prob.ndir, -1), prob.weights,
                                     storage)

@@ -135,14 +135,16 @@ def test_exact_shift_is_bit_exact():
     ((wl.BC_INFLOW, wl.BC_INFLOW, wl.BC_INFLOW, wl.BC_OUTFLOW, wl.BC_PERIODIC, wl.BC_PERIODIC), 6),
 ])
 def test_tile_shapes_are_bit_identical(bc, planes):
-    """Tile shape changes which cells take the boundary path; results must not move."""
+    """Tile shape and z-range lengths change which cells take which kernel
+    (main or general) and where the z-march starts; results must not move."""
     p = wl.random_problem(41, shape=(12, 16, 140), npoints=50, steps=2, bc=bc,
                           inflow_planes=planes)
-    ref = gh.run_problem(p, storage=L().LBRT_FP32, tile="64x1x1")
-    for tile in ("32x2x1", "16x4x1", "16x2x2", "8x8x1", "16x1x4", "4x4x4"):
-        got = gh.run_problem(p, storage=L().LBRT_FP32, tile=tile)
-        assert np.array_equal(got["I"], ref["I"]), tile
-        assert np.array_equal(got["E"], ref["E"]), tile
+    ref = gh.run_problem(p, storage=L().LBRT_FP32, tile="64x1")
+    for tile, zlen, zg in (("32x2", None, None), ("16x4", None, None), ("8x8", None, None),
+                           ("64x1", 1, 1), ("64x1", 5, 3), ("64x1", 12, 12), ("32x2", 7, 2)):
+        got = gh.run_problem(p, storage=L().LBRT_FP32, tile=tile, zlen=zlen, zlen_general=zg)
+        assert np.array_equal(got["I"], ref["I"]), (tile, zlen, zg)
+        assert np.array_equal(got["E"], ref["E"]), (tile, zlen, zg)
 
 
 def test_repeat_runs_are_bit_identical():
