@@ -157,6 +157,34 @@ int lbrt_step(lbrt_ctx *ctx, void *I_a, void *I_b,
               const float *vel, const lbrt_inflow *inflow, int32_t ninflow,
               int32_t nsteps, void *E, void *F, double *diag, void *stream);
 
+/*
+ * Adjoint of one step, for the reverse sweep of a run whose objective is
+ *   L = sum over the states I^n entering the run's steps of the energy that
+ *       streams out through face detector_face (diag[1 + face] of lbrt_step).
+ * Not in the paper: the exact transpose of its implicit step (Sec. 3.3, and
+ * App. B for a moving fluid), which is linear in the populations.  For step
+ * n (I^(n+1) = C(S I^n), S the pull of eq. (interp), C the collision):
+ *   lam_out   = d + S^T (dC/dI*)^T lam_next   (d: detector weights on the face),
+ *   g_*      += (dC/d field)^T lam_next       per cell.
+ *   I_n       device, the state entering the forward step (storage type);
+ *   lam_next  device, adjoint of the state after the step (same type; zero
+ *             for the last step); lam_out receives the adjoint of I_n and
+ *             must not overlap lam_next;
+ *   detector_face  0..5 (-x,+x,-y,+y,-z,+z), or -1 for no detector term;
+ *   g_kappa_a, g_kappa_s, g_eta  device, ncell each, float64 for FP64
+ *             storage and float32 otherwise; the step's gradients are ADDED;
+ *   kappa_a, kappa_s, eta, vel, inflow  the forward step's inputs (the inflow
+ *             ghosts fix the point of linearisation only).
+ * Supported: FP32 and FP64 storage, the implicit collision with lambda = 0,
+ * static or moving fluid (else LBRT_E_UNSUPPORTED).  The first call
+ * allocates a context-owned work buffer of one state.
+ */
+int lbrt_adjoint_step(lbrt_ctx *ctx, const void *I_n, const void *lam_next, void *lam_out,
+                      int32_t detector_face, void *g_kappa_a, void *g_kappa_s, void *g_eta,
+                      const float *kappa_a, const float *kappa_s, const float *eta,
+                      const float *vel, const lbrt_inflow *inflow, int32_t ninflow,
+                      void *stream);
+
 /* Moments E = sum_i I_i and F = sum_i n_i I_i (eq. moments_discrete) of a
  * stored state I; E, F as in lbrt_step (either may be NULL). */
 int lbrt_moments(lbrt_ctx *ctx, const void *I, void *E, void *F, void *stream);

@@ -21,6 +21,11 @@ What one step computes (Weih et al. 2020, Sec. 3.3 "Numerical procedure"):
    * moving fluid: the implicit mixed-frame equation of App. B, with the
      fluid-frame energy density J from eq. (J).
 
+The adjoint part (``stream_transpose``, ``collide_moving_vjp``,
+``detected_energy_gradient``) differentiates this same forward run in reverse
+mode; it is pinned by the transpose identity and by finite differences of
+the forward run.
+
 Conventions: populations are weight-absorbed (I_i = w_i I(n_i)); kappa_s in
 the inputs is the paper's kappa_0 and ``lam`` is lambda = 3 kappa_1 / kappa_0
 (eq. rte_gray_bgkform); arrays are ``[dir, z, y, x]``.
@@ -440,3 +445,123 @@ def detector_weights(prob, face: int = FACE_PX) -> np.ndarray:
         if leaving:
             d[(i,) + tuple(layer)] = prob.dt * abs(nc) / prob.dx
     return d
+
+
+def stream_transpose(nu: np.ndarray, prob) -> np.ndarray:
+    """Transpose of the streaming map I -> I* with vacuum ghosts.
+
+    The pull of eq. (interp) writes I*_i(r) = sum_b w_b I_i(r - b.s_i), so its
+    transpose scatters each streamed value back to the cells it was pulled
+    from: out_i(r - b.s_i) += w_b nu_i(r).  Sources outside the box are ghost
+    values, not state, and receive nothing (periodic axes wrap).  Written as
+    that scatter, tap by tap, so it is checked against ``stream`` by the
+    identity <A x, y> = <x, A^T y>."""
+    out = np.zeros_like(nu, dtype=np.float64)
+    zz, yy, xx = np.meshgrid(np.arange(prob.nz), np.arange(prob.ny), np.arange(prob.nx),
+                             indexing="ij")
+    for i in range(prob.ndir):
+        s = shift_signs(prob.dirs[i])
+        for bx, by, bz, wgt in _taps(prob.dirs[i], prob.dt, prob.dx):
+            (cz, cy, cx), (oz, oy, ox) = _wrap_and_flag(prob, zz - bz * s[2], yy - by * s[1],
+                                                        xx - bx * s[0])
+            inside = ~(oz | oy | ox)
+            # one tap maps distinct cells to distinct sources (a shift, wrapped
+            # on periodic axes), so a plain indexed add accumulates exactly
+            out[i][cz[inside], cy[inside], cx[inside]] += wgt * nu[i][inside]
+    return out
+
+
+def _moving_terms(dirs, w, ka, k0, et, v, dt, Istar):
+    """The affine form of the moving-fluid collision used by ``collide_moving``:
+    I_i = p_i + q_i J with J = X / (1 - Y); returns its pieces."""
+    v2 = v[0] ** 2 + v[1] ** 2 + v[2] ** 2
+    W = 1.0 / np.sqrt(1.0 - v2)
+    n = len(w)
+    D = np.stack([1.0 - (v[0] * dirs[i, 0] + v[1] * dirs[i, 1] + v[2] * dirs[i, 2])
+                  for i in range(n)])
+    a = 1.0 / (1.0 + dt * W * D * (ka + k0))
+    c = np.stack([dt * w[i] / (W ** 3 * D[i] ** 3) for i in range(n)])
+    p = a * (Istar + c * et)
+    q = a * c * k0
+    X = W ** 2 * np.sum(D ** 2 * p, axis=0)
+    Y = W ** 2 * np.sum(D ** 2 * q, axis=0)
+    return W, D, a, c, p, q, X, Y
+
+
+def collide_moving_vjp(Istar, mu, dirs, w, kappa_a, kappa_0, eta, vel, dt):
+    """Vector-Jacobian product of ``collide_moving`` at the streamed state
+    Istar with the cotangent mu (both [dir, ...]).
+
+    The collision is I_i = p_i + q_i J, J = X / (1 - Y), with
+    a_i = 1 / (1 + dt W D_i (ka + k0)), p_i = a_i (I*_i + c_i eta),
+    q_i = a_i c_i k0, c_i = dt w_i / (W^3 D_i^3), X = W^2 sum D_i^2 p_i and
+    Y = W^2 sum D_i^2 q_i (the sums are eq. (J) written with D_i = 1 - v.n_i).
+    Returns (nu = (dI/dI*)^T mu, and the cotangents of kappa_a, kappa_0, eta),
+    by the chain rule through exactly these expressions."""
+    ka, k0, et = _f64(kappa_a), _f64(kappa_0), _f64(eta)
+    v = _f64(vel)
+    W, D, a, c, p, q, X, Y = _moving_terms(dirs, w, ka, k0, et, v, dt, Istar)
+    J = X / (1.0 - Y)
+    # cotangents of J and of each p_i, q_i
+    gJ = np.sum(mu * q, axis=0)
+    gp = mu.copy()
+    gq = mu * J
+    # J = X / (1 - Y)
+    gX = gJ / (1.0 - Y)
+    gY = gJ * X / (1.0 - Y) ** 2
+    gp = gp + gX * W ** 2 * D ** 2
+    gq = gq + gY * W ** 2 * D ** 2
+    # p_i = a_i (I*_i + c_i eta), q_i = a_i c_i k0
+    nu = gp * a
+    g_eta = np.sum(gp * a * c, axis=0)
+    g_k0 = np.sum(gq * a * c, axis=0)
+    ga = gp * (Istar + c * et) + gq * c * k0
+    # a_i = 1 / (1 + dt W D_i (ka + k0)): da/dk = -a^2 dt W D_i for ka and k0
+    dadk = -a ** 2 * dt * W * D
+    g_ka = np.sum(ga * dadk, axis=0)
+    g_k0 = g_k0 + g_ka
+    return nu, g_ka, g_k0, g_eta
+
+
+def detected_energy(prob, steps: int, face: int = FACE_PX, I0=None) -> float:
+    """L = sum over the states I^0 .. I^(steps-1) entering each step of the
+    energy that streams out through ``face`` (the detector of
+    ``detector_weights``)."""
+    d = detector_weights(prob, face)
+    I = np.array(prob.I0 if I0 is None else I0, dtype=np.float64, copy=True)
+    L = 0.0
+    for _ in range(steps):
+        L += float(np.sum(d * I))
+        I = step(I, prob)
+    return L
+
+
+def detected_energy_gradient(prob, steps: int, face: int = FACE_PX, I0=None):
+    """L of ``detected_energy`` and its gradient with respect to the per-cell
+    kappa_a, kappa_s (= kappa_0) and eta, by reverse-mode differentiation of
+    the run: lambda^n = d + S^T (dC/dI*)^T lambda^(n+1), lambda^steps = 0, where
+    S is the streaming map and C the moving-fluid collision (a static fluid is
+    the case v = 0).  Stores every state (small boxes only)."""
+    vel = prob.vel if prob.vel is not None else np.zeros((3,) + prob.shape)
+    d = detector_weights(prob, face)
+    I = np.array(prob.I0 if I0 is None else I0, dtype=np.float64, copy=True)
+    states = []
+    L = 0.0
+    for _ in range(steps):
+        states.append(I)
+        L += float(np.sum(d * I))
+        I = collide_moving(stream(I, prob), prob.dirs, prob.weights, prob.kappa_a,
+                           prob.kappa_s, prob.eta, vel, prob.dt)
+    lam = np.zeros_like(I)
+    g_ka = np.zeros(prob.shape)
+    g_ks = np.zeros(prob.shape)
+    g_eta = np.zeros(prob.shape)
+    for n in range(steps - 1, -1, -1):
+        Istar = stream(states[n], prob)
+        nu, a1, a2, a3 = collide_moving_vjp(Istar, lam, prob.dirs, prob.weights, prob.kappa_a,
+                                            prob.kappa_s, prob.eta, vel, prob.dt)
+        g_ka += a1
+        g_ks += a2
+        g_eta += a3
+        lam = d + stream_transpose(nu, prob)
+    return L, g_ka, g_ks, g_eta

@@ -7,7 +7,7 @@ marshal arguments (torch tensors -> device pointers, the current torch
 stream -> hipStream_t).  Every step of the computation runs in the HIP
 kernels of ``_lib/liblbrt.so``; there is no Python or CPU fallback, and
 importing this module fails loudly when the library has not been built
-(``python -m paper_2007_05718_amd.build``).
+(``python paper_2007_05718_amd/build.py``).
 """
 from __future__ import annotations
 
@@ -65,7 +65,7 @@ def _load():
     import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"lbrt HIP library missing at {LIB_PATH}; build it with "
-                          "`python -m paper_2007_05718_amd.build`")
+                          "`python paper_2007_05718_amd/build.py`")
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)
     lib.lbrt_validate.argtypes = [ctypes.POINTER(lbrt_desc)]
@@ -81,6 +81,9 @@ def _load():
     lib.lbrt_moments.restype = ctypes.c_int
     lib.lbrt_convert.argtypes = [vp, vp, i32, vp, i32, vp]
     lib.lbrt_convert.restype = ctypes.c_int
+    lib.lbrt_adjoint_step.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp,
+                                      ctypes.POINTER(lbrt_inflow), i32, vp]
+    lib.lbrt_adjoint_step.restype = ctypes.c_int
     lib.lbrt_last_error.argtypes = []
     lib.lbrt_last_error.restype = ctypes.c_char_p
     return lib
@@ -222,6 +225,18 @@ def _moment_dtype(storage: int):
     return torch.float64 if storage == LBRT_FP64 else torch.float32
 
 
+def _inflow_planes(inflow):
+    if not inflow:
+        return None, 0
+    nin = len(inflow)
+    planes = (lbrt_inflow * nin)()
+    for j, (face, direction, vals) in enumerate(inflow):
+        planes[j].face = int(face)
+        planes[j].dir = int(direction)
+        planes[j].values = _ptr(vals, f"inflow[{j}]", dtype=_torch().float32).value
+    return planes, nin
+
+
 def lbrt_step(ctx: Context, I_a, I_b, kappa_a, kappa_s, eta, vel=None, inflow=None,
               nsteps: int = 1, E=None, F=None, diag=None, stream=None) -> None:
     """``nsteps`` steps, ping-pong between I_a and I_b (result in I_b when
@@ -229,15 +244,7 @@ def lbrt_step(ctx: Context, I_a, I_b, kappa_a, kappa_s, eta, vel=None, inflow=No
     d = ctx.desc
     n, nc = d.ndir, d.ncell
     st = d.c.storage
-    planes = None
-    nin = 0
-    if inflow:
-        nin = len(inflow)
-        planes = (lbrt_inflow * nin)()
-        for j, (face, direction, vals) in enumerate(inflow):
-            planes[j].face = int(face)
-            planes[j].dir = int(direction)
-            planes[j].values = _ptr(vals, f"inflow[{j}]", dtype=_torch().float32).value
+    planes, nin = _inflow_planes(inflow)
     f32 = _torch().float32
     rc = _lib.lbrt_step(
         ctx.handle, _ptr(I_a, "I_a", n * nc, _pop_dtype(st)),
@@ -247,6 +254,28 @@ def lbrt_step(ctx: Context, I_a, I_b, kappa_a, kappa_s, eta, vel=None, inflow=No
         _ptr(E, "E", nc, _moment_dtype(st)), _ptr(F, "F", 3 * nc, _moment_dtype(st)),
         _ptr(diag, "diag", LBRT_DIAG_LEN, _torch().float64), _stream(stream))
     _check(rc)
+
+
+def lbrt_adjoint_step(ctx: Context, I_n, lam_next, lam_out, detector_face: int, g_kappa_a,
+                      g_kappa_s, g_eta, kappa_a, kappa_s, eta, vel=None, inflow=None,
+                      stream=None) -> None:
+    """Adjoint of one step (see include/lbrt.h): lam_out = d + S^T (dC/dI*)^T
+    lam_next, and the step's field gradients are added into g_*."""
+    d = ctx.desc
+    n, nc = d.ndir, d.ncell
+    st = d.c.storage
+    planes, nin = _inflow_planes(inflow)
+    f32 = _torch().float32
+    gdt = _moment_dtype(st)
+    _check(_lib.lbrt_adjoint_step(
+        ctx.handle, _ptr(I_n, "I_n", n * nc, _pop_dtype(st)),
+        _ptr(lam_next, "lam_next", n * nc, _pop_dtype(st)),
+        _ptr(lam_out, "lam_out", n * nc, _pop_dtype(st)), int(detector_face),
+        _ptr(g_kappa_a, "g_kappa_a", nc, gdt), _ptr(g_kappa_s, "g_kappa_s", nc, gdt),
+        _ptr(g_eta, "g_eta", nc, gdt),
+        _ptr(kappa_a, "kappa_a", nc, f32), _ptr(kappa_s, "kappa_s", nc, f32),
+        _ptr(eta, "eta", nc, f32), _ptr(vel, "vel", 3 * nc, f32), planes, nin,
+        _stream(stream)))
 
 
 def lbrt_moments(ctx: Context, I, E=None, F=None, stream=None) -> None:
@@ -269,7 +298,7 @@ def lbrt_convert(ctx: Context, src, src_storage: int, dst, dst_storage: int,
 def exported_symbols() -> list:
     """Names of the C entry points the binding wraps."""
     return ["lbrt_validate", "lbrt_init", "lbrt_destroy", "lbrt_step", "lbrt_moments",
-            "lbrt_convert", "lbrt_last_error"]
+            "lbrt_convert", "lbrt_adjoint_step", "lbrt_last_error"]
 
 
 def library():

@@ -1,7 +1,8 @@
 """Build the lbrt HIP library for gfx950 in-tree.
 
 Compiles every source under csrc/ with hipcc (in parallel) and links
-``_lib/liblbrt.so``.  Run ``python -m paper_2007_05718_amd.build`` or call
+``_lib/liblbrt.so``.  Run ``python paper_2007_05718_amd/build.py`` (a plain
+script: importing the package would load the library it builds) or call
 ``build()``; it always recompiles.
 """
 from __future__ import annotations

@@ -57,6 +57,7 @@ struct lbrt_ctx {
   double *partials = nullptr;     // per-block sums of the step kernel
   int partials_cap = 0;
   InflowArgs *inflow_dev = nullptr; // ghost-plane table of the current call
+  void *adj_work = nullptr;         // one state: the adjoint's nu buffer
   InflowArgs inflow_host{};         // what inflow_dev holds
   bool inflow_valid = false;
   TileShape tile{64, 1};
@@ -277,6 +278,70 @@ int plan_tiles(lbrt_ctx *c, int variant, bool zlo_inflow, bool zhi_inflow) {
   return LBRT_OK;
 }
 
+// Checks the inflow planes of a call and fills the per-slot ghost table.
+int build_inflow(const lbrt_ctx *c, const lbrt_inflow *inflow, int32_t ninflow, InflowArgs &in,
+                 bool &xghosts, bool &zghosts) {
+  const lbrt_desc &d = c->desc;
+  if (ninflow < 0 || ninflow > LBRT_MAX_INFLOW)
+    return fail(LBRT_E_INVAL, "ninflow = %d outside [0, %d]", ninflow, (int)LBRT_MAX_INFLOW);
+  if (ninflow > 0 && !inflow) return fail(LBRT_E_INVAL, "inflow is NULL but ninflow > 0");
+  std::memset(&in, 0, sizeof(in));
+  in.n = ninflow;
+  for (int j = 0; j < ninflow; ++j) {
+    const lbrt_inflow &pl = inflow[j];
+    if (pl.face < 0 || pl.face > 5) return fail(LBRT_E_INVAL, "inflow[%d].face = %d", j, pl.face);
+    if (d.bc[pl.face] != LBRT_BC_INFLOW)
+      return fail(LBRT_E_INVAL, "inflow[%d]: face %d is not an inflow face", j, pl.face);
+    if (pl.dir < 0 || pl.dir >= d.ndir) return fail(LBRT_E_INVAL, "inflow[%d].dir = %d", j, pl.dir);
+    if (!pl.values) return fail(LBRT_E_INVAL, "inflow[%d].values is NULL", j);
+    const int axis = pl.face >> 1;
+    const double comp = c->dirs[3 * pl.dir + axis];
+    const bool enters = (pl.face & 1) == 0 ? comp > 0.0 : comp < 0.0;
+    if (!enters)
+      return fail(LBRT_E_INVAL, "inflow[%d]: direction %d does not enter through face %d", j,
+                  pl.dir, pl.face);
+    for (int k = 0; k < j; ++k)
+      if (in.face[k] == pl.face && in.dir[k] == pl.dir)
+        return fail(LBRT_E_INVAL, "inflow[%d]: (face %d, dir %d) listed twice", j, pl.face,
+                    pl.dir);
+    in.face[j] = pl.face;
+    in.dir[j] = pl.dir;
+    in.ptr[j] = pl.values;
+  }
+  // per processing slot and axis: the ghost plane that slot pulls from
+  for (int k = 0; k < LBRT_MAX_DIRS; ++k)
+    for (int a = 0; a < 3; ++a) in.ghost[k][a] = nullptr;
+  xghosts = zghosts = false;
+  for (int j = 0; j < ninflow; ++j) {
+    xghosts |= (in.face[j] >> 1) == 0;
+    zghosts |= (in.face[j] >> 1) == 2;
+  }
+  for (int k = 0; k < d.ndir; ++k) {
+    const int i = c->order[k];
+    for (int a = 0; a < 3; ++a) {
+      const double comp = c->dirs[3 * i + a];
+      if (comp == 0.0) continue;
+      const int face = 2 * a + (comp > 0.0 ? 0 : 1);
+      for (int j = 0; j < ninflow; ++j)
+        if (in.face[j] == face && in.dir[j] == i) in.ghost[k][a] = in.ptr[j];
+    }
+  }
+  return LBRT_OK;
+}
+
+// Sends the ghost table to the device, in stream order, only when it differs
+// from the previous call's (pageable source: the host copy may change right
+// after the call).
+int upload_inflow(lbrt_ctx *c, const InflowArgs &in, hipStream_t s) {
+  if (!c->inflow_valid || std::memcmp(&c->inflow_host, &in, sizeof(in)) != 0) {
+    hipError_t e0 = hipMemcpyAsync(c->inflow_dev, &in, sizeof(in), hipMemcpyHostToDevice, s);
+    if (e0 != hipSuccess) return hip_fail(e0, "uploading the inflow table");
+    c->inflow_host = in;
+    c->inflow_valid = true;
+  }
+  return LBRT_OK;
+}
+
 int total_partials(const KParams &p) { return p.nblocks + p.ngeneral + zface_blocks(p); }
 }  // namespace
 
@@ -466,6 +531,7 @@ void lbrt_destroy(lbrt_ctx *c) {
   if (c->inflow_dev) (void)hipFree(c->inflow_dev);
   for (int v = 0; v < 2; ++v)
     if (c->general_dev[v]) (void)hipFree(c->general_dev[v]);
+  if (c->adj_work) (void)hipFree(c->adj_work);
   delete c;
 }
 
@@ -484,51 +550,10 @@ int lbrt_step(lbrt_ctx *c, void *I_a, void *I_b, const float *kappa_a, const flo
   if (!kappa_a || !kappa_s || !eta) return fail(LBRT_E_INVAL, "kappa_a, kappa_s, eta required");
   if (d.moving_fluid && !vel) return fail(LBRT_E_INVAL, "moving fluid: vel is required");
   if (!d.moving_fluid && vel) return fail(LBRT_E_INVAL, "vel given but moving_fluid is off");
-  if (ninflow < 0 || ninflow > LBRT_MAX_INFLOW)
-    return fail(LBRT_E_INVAL, "ninflow = %d outside [0, %d]", ninflow, (int)LBRT_MAX_INFLOW);
-  if (ninflow > 0 && !inflow) return fail(LBRT_E_INVAL, "inflow is NULL but ninflow > 0");
   InflowArgs in;
-  std::memset(&in, 0, sizeof(in));
-  in.n = ninflow;
-  for (int j = 0; j < ninflow; ++j) {
-    const lbrt_inflow &pl = inflow[j];
-    if (pl.face < 0 || pl.face > 5) return fail(LBRT_E_INVAL, "inflow[%d].face = %d", j, pl.face);
-    if (d.bc[pl.face] != LBRT_BC_INFLOW)
-      return fail(LBRT_E_INVAL, "inflow[%d]: face %d is not an inflow face", j, pl.face);
-    if (pl.dir < 0 || pl.dir >= d.ndir) return fail(LBRT_E_INVAL, "inflow[%d].dir = %d", j, pl.dir);
-    if (!pl.values) return fail(LBRT_E_INVAL, "inflow[%d].values is NULL", j);
-    const int axis = pl.face >> 1;
-    const double comp = c->dirs[3 * pl.dir + axis];
-    const bool enters = (pl.face & 1) == 0 ? comp > 0.0 : comp < 0.0;
-    if (!enters)
-      return fail(LBRT_E_INVAL, "inflow[%d]: direction %d does not enter through face %d", j,
-                  pl.dir, pl.face);
-    for (int k = 0; k < j; ++k)
-      if (in.face[k] == pl.face && in.dir[k] == pl.dir)
-        return fail(LBRT_E_INVAL, "inflow[%d]: (face %d, dir %d) listed twice", j, pl.face,
-                    pl.dir);
-    in.face[j] = pl.face;
-    in.dir[j] = pl.dir;
-    in.ptr[j] = pl.values;
-  }
-  // per processing slot and axis: the ghost plane that slot pulls from
-  for (int k = 0; k < LBRT_MAX_DIRS; ++k)
-    for (int a = 0; a < 3; ++a) in.ghost[k][a] = nullptr;
-  bool xghosts = false, zghosts = false;
-  for (int j = 0; j < ninflow; ++j) {
-    xghosts |= (in.face[j] >> 1) == 0;
-    zghosts |= (in.face[j] >> 1) == 2;
-  }
-  for (int k = 0; k < d.ndir; ++k) {
-    const int i = c->order[k];
-    for (int a = 0; a < 3; ++a) {
-      const double comp = c->dirs[3 * i + a];
-      if (comp == 0.0) continue;
-      const int face = 2 * a + (comp > 0.0 ? 0 : 1);
-      for (int j = 0; j < ninflow; ++j)
-        if (in.face[j] == face && in.dir[j] == i) in.ghost[k][a] = in.ptr[j];
-    }
-  }
+  bool xghosts, zghosts;
+  int rc0 = build_inflow(c, inflow, ninflow, in, xghosts, zghosts);
+  if (rc0 != LBRT_OK) return rc0;
   hipStream_t s = static_cast<hipStream_t>(stream);
   KParams p = make_params(c);
   if (xghosts) p.flags |= KF_XGHOSTS;
@@ -542,15 +567,8 @@ int lbrt_step(lbrt_ctx *c, void *I_a, void *I_b, const float *kappa_a, const flo
   }
   int rc = ensure_partials(c, total_partials(p));
   if (rc != LBRT_OK) return rc;
-  // The ghost table lives in device memory; it is re-sent (in stream order,
-  // from pageable memory, so the host copy may change right after) only when
-  // this call's planes differ from the previous call's.
-  if (!c->inflow_valid || std::memcmp(&c->inflow_host, &in, sizeof(in)) != 0) {
-    hipError_t e0 = hipMemcpyAsync(c->inflow_dev, &in, sizeof(in), hipMemcpyHostToDevice, s);
-    if (e0 != hipSuccess) return hip_fail(e0, "lbrt_step: uploading the inflow table");
-    c->inflow_host = in;
-    c->inflow_valid = true;
-  }
+  rc = upload_inflow(c, in, s);
+  if (rc != LBRT_OK) return rc;
   StepLauncher launch = step_launcher(d.storage, c->bucket, d.moving_fluid != 0);
   if (!launch) return fail(LBRT_E_UNSUPPORTED, "no kernel for storage %d, %d directions",
                            d.storage, d.ndir);
@@ -584,6 +602,51 @@ int lbrt_step(lbrt_ctx *c, void *I_a, void *I_b, const float *kappa_a, const flo
       if (e != hipSuccess) return hip_fail(e, "lbrt_step: reducing diagnostics");
     }
   }
+  return LBRT_OK;
+}
+
+int lbrt_adjoint_step(lbrt_ctx *c, const void *I_n, const void *lam_next, void *lam_out,
+                      int32_t detector_face, void *g_kappa_a, void *g_kappa_s, void *g_eta,
+                      const float *kappa_a, const float *kappa_s, const float *eta,
+                      const float *vel, const lbrt_inflow *inflow, int32_t ninflow,
+                      void *stream) {
+  if (!c) return fail(LBRT_E_INVAL, "ctx is NULL");
+  const lbrt_desc &d = c->desc;
+  if (d.storage != LBRT_FP32 && d.storage != LBRT_FP64)
+    return fail(LBRT_E_UNSUPPORTED, "the adjoint needs FP32 or FP64 storage");
+  if (d.collision != LBRT_COLL_IMPLICIT || d.lambda_aniso != 0.0)
+    return fail(LBRT_E_UNSUPPORTED, "the adjoint covers the implicit collision with lambda = 0");
+  if (!I_n || !lam_next || !lam_out) return fail(LBRT_E_INVAL, "I_n, lam_next, lam_out required");
+  if (!g_kappa_a || !g_kappa_s || !g_eta) return fail(LBRT_E_INVAL, "gradients required");
+  if (!kappa_a || !kappa_s || !eta) return fail(LBRT_E_INVAL, "kappa_a, kappa_s, eta required");
+  if (d.moving_fluid && !vel) return fail(LBRT_E_INVAL, "moving fluid: vel is required");
+  if (!d.moving_fluid && vel) return fail(LBRT_E_INVAL, "vel given but moving_fluid is off");
+  if (detector_face < -1 || detector_face > 5)
+    return fail(LBRT_E_INVAL, "detector_face = %d outside [-1, 5]", detector_face);
+  const int64_t ncell = (int64_t)d.nx * d.ny * d.nz;
+  const size_t bytes = storage_bytes(d.storage) * (size_t)ncell * d.ndir;
+  const char *ln = static_cast<const char *>(lam_next), *lo = static_cast<const char *>(lam_out);
+  if (ln < lo + bytes && lo < ln + bytes) return fail(LBRT_E_INVAL, "lam_next and lam_out overlap");
+  InflowArgs in;
+  bool xghosts, zghosts;
+  int rc = build_inflow(c, inflow, ninflow, in, xghosts, zghosts);
+  if (rc != LBRT_OK) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!c->adj_work) {
+    hipError_t e = hipMalloc(&c->adj_work, bytes);
+    if (e != hipSuccess) {
+      c->adj_work = nullptr;
+      return fail(LBRT_E_NOMEM, "hipMalloc(adjoint work buffer, %zu bytes): %s", bytes,
+                  hipGetErrorString(e));
+    }
+  }
+  rc = upload_inflow(c, in, s);
+  if (rc != LBRT_OK) return rc;
+  KParams p = make_params(c);
+  hipError_t e = launch_adjoint(d.storage, I_n, lam_next, lam_out, c->adj_work, detector_face,
+                                g_kappa_a, g_kappa_s, g_eta, kappa_a, kappa_s, eta, vel,
+                                c->tab_dev, p, c->inflow_dev, s);
+  if (e != hipSuccess) return hip_fail(e, "lbrt_adjoint_step");
   return LBRT_OK;
 }
 

@@ -121,6 +121,13 @@ hipError_t launch_convert(const void *src, int src_storage, void *dst, int dst_s
 hipError_t launch_diag_reduce(const double *partials, int nblocks, double *diag, int first_step,
                               hipStream_t s);
 hipError_t launch_fill_f64(double *p, int n, double v, hipStream_t s);
+// Adjoint of one step (FP32 or FP64 storage): nu is a work buffer of one
+// state; gradients are added into g_ka, g_ks, g_eta.
+hipError_t launch_adjoint(int storage, const void *I, const void *lam_next, void *lam_out,
+                          void *nu, int face, void *g_ka, void *g_ks, void *g_eta,
+                          const float *ka, const float *ks, const float *eta, const float *vel,
+                          const void *tab, const KParams &p, const InflowArgs *inflow,
+                          hipStream_t s);
 // Blocks of the z-face flux kernel (0 on a periodic z axis), and its launch:
 // per-block partials in the step kernel's format.
 int zface_blocks(const KParams &p);

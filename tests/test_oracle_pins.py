@@ -425,3 +425,92 @@ def test_crossing_beams_superpose():
     Ia, Ib, Iab = orc.run(pa), orc.run(pb), orc.run(pab)
     assert np.max(np.abs(Iab - (Ia + Ib))) < 1e-15
     assert Ia.sum() > 0 and Ib.sum() > 0
+
+
+# ---------------------------------------------------------------------------
+# Adjoint of a run (gradient of the energy detected on a face)
+# ---------------------------------------------------------------------------
+def _f64_fields(p):
+    """Coefficient fields in float64, so that finite-difference steps are exact."""
+    p.kappa_a = np.asarray(p.kappa_a, dtype=np.float64)
+    p.kappa_s = np.asarray(p.kappa_s, dtype=np.float64)
+    p.eta = np.asarray(p.eta, dtype=np.float64)
+    if p.vel is not None:
+        p.vel = np.asarray(p.vel, dtype=np.float64)
+    return p
+
+
+@pytest.mark.parametrize("bc", [(wl.BC_OUTFLOW,) * 6, (wl.BC_PERIODIC,) * 6,
+                                (wl.BC_INFLOW, wl.BC_OUTFLOW, wl.BC_PERIODIC, wl.BC_PERIODIC,
+                                 wl.BC_OUTFLOW, wl.BC_INFLOW)])
+def test_stream_transpose_is_the_transpose(bc):
+    """<S x, y> = <x, S^T y> for the pull of eq. (interp) with vacuum ghosts."""
+    p = _problem(shape=(5, 6, 7), npoints=26, bc=bc, seed=8, inflow_planes=2)
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((p.ndir,) + p.shape)
+    y = rng.standard_normal((p.ndir,) + p.shape)
+    Sx = np.stack([orc.stream_direction(x[i], i, p, ghosts=False) for i in range(p.ndir)])
+    lhs = float(np.sum(Sx * y))
+    rhs = float(np.sum(x * orc.stream_transpose(y, p)))
+    assert abs(lhs - rhs) < 1e-12 * np.sum(np.abs(Sx * y))
+
+
+@pytest.mark.parametrize("vmag", [0.0, 0.45])
+def test_collision_vjp_matches_finite_differences(vmag):
+    """The vector-Jacobian product of the moving collision (and of the static
+    one at v = 0) against central differences of the forward collision."""
+    dirs, w = wl.lebedev(26)
+    rng = np.random.default_rng(2)
+    Is = rng.uniform(0.1, 1.0, (26, 3)) * w[:, None]
+    mu = rng.standard_normal((26, 3))
+    ka = np.array([0.7, 30.0, 0.01])
+    k0 = np.array([0.4, 0.02, 50.0])
+    et = np.array([0.3, 5.0, 0.0])
+    v = rng.standard_normal((3, 3))
+    v *= vmag / np.linalg.norm(v, axis=0, keepdims=True)
+    dt = 0.5
+    nu, gka, gk0, geta = orc.collide_moving_vjp(Is, mu, dirs, w, ka, k0, et, v, dt)
+    f = lambda Is, ka, k0, et: np.sum(mu * orc.collide_moving(Is, dirs, w, ka, k0, et, v, dt),
+                                      axis=0)
+    for c in range(3):
+        for name, g, arr in (("ka", gka, ka), ("k0", gk0, k0), ("eta", geta, et)):
+            h = 1e-5 * max(1.0, abs(arr[c]))
+            up, dn = arr.copy(), arr.copy()
+            up[c] += h
+            dn[c] -= h
+            args_up = {"ka": (Is, up, k0, et), "k0": (Is, ka, up, et), "eta": (Is, ka, k0, up)}[name]
+            args_dn = {"ka": (Is, dn, k0, et), "k0": (Is, ka, dn, et), "eta": (Is, ka, k0, dn)}[name]
+            fd = (f(*args_up)[c] - f(*args_dn)[c]) / (2 * h)
+            assert abs(fd - g[c]) < 1e-7 * max(1.0, abs(fd)), (name, c, fd, g[c])
+        for i in (0, 7, 25):
+            e = np.zeros_like(Is)
+            e[i, c] = 1e-6
+            fd = (f(Is + e, ka, k0, et)[c] - f(Is - e, ka, k0, et)[c]) / 2e-6
+            assert abs(fd - nu[i, c]) < 1e-7 * max(1.0, abs(fd))
+
+
+@pytest.mark.parametrize("moving,bc,planes", [
+    (False, (wl.BC_OUTFLOW,) * 6, 0),
+    (True, (wl.BC_OUTFLOW, wl.BC_OUTFLOW, wl.BC_PERIODIC, wl.BC_PERIODIC, wl.BC_OUTFLOW,
+            wl.BC_INFLOW), 2),
+])
+def test_detected_energy_gradient_matches_finite_differences(moving, bc, planes):
+    """Reverse-mode gradient of the energy leaving through +x over a 3-step run
+    against central differences of the forward run (FP64, float64 fields)."""
+    p = _f64_fields(wl.random_problem(3, shape=(5, 6, 7), npoints=14, steps=3,
+                                      moving_fluid=moving, vmax=0.5, bc=bc,
+                                      inflow_planes=planes))
+    L, gka, gks, geta = orc.detected_energy_gradient(p, 3)
+    assert abs(L - orc.detected_energy(p, 3)) < 1e-13 * abs(L)
+    gmax = max(np.abs(gka).max(), np.abs(gks).max(), np.abs(geta).max())
+    for cell in [(2, 3, 6), (4, 5, 5), (1, 2, 5), (3, 0, 6)]:
+        for fld, g in ((p.kappa_a, gka), (p.kappa_s, gks), (p.eta, geta)):
+            base = fld[cell]
+            h = 1e-4 * max(1.0, abs(base))
+            fld[cell] = base + h
+            Lp = orc.detected_energy(p, 3)
+            fld[cell] = base - h
+            Lm = orc.detected_energy(p, 3)
+            fld[cell] = base
+            fd = (Lp - Lm) / (2 * h)
+            assert abs(fd - g[cell]) < 1e-6 * gmax + 1e-6 * abs(fd), (cell, fd, g[cell])
