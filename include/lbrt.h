@@ -195,6 +195,46 @@ int lbrt_moments(lbrt_ctx *ctx, const void *I, void *E, void *F, void *stream);
 int lbrt_convert(lbrt_ctx *ctx, const void *src, int32_t src_storage,
                  void *dst, int32_t dst_storage, void *stream);
 
+/*
+ * Tiling of a context's step kernels: xy tiles of tx x ty cells (tx * ty = 64,
+ * tx a power of two) and z ranges of zlen planes (main kernel) and
+ * zlen_general planes (boundary tiles).  Tiling changes speed only: results
+ * are bit-identical for every choice.  The autotuner calls this.
+ */
+int lbrt_set_tiling(lbrt_ctx *ctx, int32_t tx, int32_t ty, int32_t zlen, int32_t zlen_general);
+
+/*
+ * Batched form: many independent domains (each its own context, buffers,
+ * fields and step count) advanced together by ONE persistent kernel launch.
+ * Not in the paper.  A domain runs nsteps steps as lbrt_step would (result in
+ * I_b when nsteps is odd), without diagnostics or inflow ghosts; E, F (or
+ * NULL) receive its moments after the last step.  Every domain must share the
+ * storage type, the direction bucket and the fluid kind of the first;
+ * supported: FP32 storage, static fluid.
+ *
+ * lbrt_batch_create builds the work queue on the host and uploads it (call it
+ * outside graph capture); it copies what it needs from the domains, whose
+ * contexts and buffers must outlive the batch.  lbrt_step_batched only
+ * enqueues kernels (a counter reset and the persistent launch) and may be
+ * captured in a hipGraph and replayed.  lbrt_batch_error reports, after the
+ * stream has finished (it synchronises), whether a queue wait exceeded its
+ * spin limit (flag != 0: the results of that run are not to be trusted).
+ */
+typedef struct {
+  lbrt_ctx *ctx;
+  void *I_a, *I_b;
+  const float *kappa_a, *kappa_s, *eta, *vel;
+  int32_t nsteps;
+  void *E, *F;
+} lbrt_domain;
+
+typedef struct lbrt_batch lbrt_batch;
+
+int lbrt_batch_create(const lbrt_domain *domains, int32_t ndomains, lbrt_batch **out);
+int lbrt_step_batched(lbrt_batch *batch, void *stream);
+int lbrt_batch_error(lbrt_batch *batch, int32_t *flag);
+void lbrt_batch_destroy(lbrt_batch *batch);
+
 /* Message describing the last error returned on the calling thread
  * (empty string if none).  The pointer stays valid until the thread's next
  * lbrt call. */

@@ -53,6 +53,13 @@ class lbrt_inflow(ctypes.Structure):
                 ("values", ctypes.c_void_p)]
 
 
+class lbrt_domain(ctypes.Structure):
+    _fields_ = [("ctx", ctypes.c_void_p), ("I_a", ctypes.c_void_p), ("I_b", ctypes.c_void_p),
+                ("kappa_a", ctypes.c_void_p), ("kappa_s", ctypes.c_void_p),
+                ("eta", ctypes.c_void_p), ("vel", ctypes.c_void_p), ("nsteps", ctypes.c_int32),
+                ("E", ctypes.c_void_p), ("F", ctypes.c_void_p)]
+
+
 class LbrtError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"lbrt error {code}: {msg}")
@@ -84,6 +91,16 @@ def _load():
     lib.lbrt_adjoint_step.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp,
                                       ctypes.POINTER(lbrt_inflow), i32, vp]
     lib.lbrt_adjoint_step.restype = ctypes.c_int
+    lib.lbrt_set_tiling.argtypes = [vp, i32, i32, i32, i32]
+    lib.lbrt_set_tiling.restype = ctypes.c_int
+    lib.lbrt_batch_create.argtypes = [ctypes.POINTER(lbrt_domain), i32, ctypes.POINTER(vp)]
+    lib.lbrt_batch_create.restype = ctypes.c_int
+    lib.lbrt_step_batched.argtypes = [vp, vp]
+    lib.lbrt_step_batched.restype = ctypes.c_int
+    lib.lbrt_batch_error.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.lbrt_batch_error.restype = ctypes.c_int
+    lib.lbrt_batch_destroy.argtypes = [vp]
+    lib.lbrt_batch_destroy.restype = None
     lib.lbrt_last_error.argtypes = []
     lib.lbrt_last_error.restype = ctypes.c_char_p
     return lib
@@ -295,10 +312,77 @@ def lbrt_convert(ctx: Context, src, src_storage: int, dst, dst_storage: int,
                              int(dst_storage), _stream(stream)))
 
 
+def lbrt_set_tiling(ctx: Context, tx: int, ty: int, zlen: int, zlen_general: int) -> None:
+    """Tile shape and z-range lengths of the context's kernels (speed only)."""
+    _check(_lib.lbrt_set_tiling(ctx.handle, int(tx), int(ty), int(zlen), int(zlen_general)))
+
+
+class Batch:
+    """Owns an ``lbrt_batch`` plan and keeps its domains' tensors alive."""
+
+    def __init__(self, handle: int, keep):
+        self.handle = ctypes.c_void_p(handle)
+        self._keep = keep
+
+    def close(self):
+        if self.handle:
+            _lib.lbrt_batch_destroy(self.handle)
+            self.handle = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lbrt_batch_create(domains) -> Batch:
+    """``domains``: sequence of dicts with keys ctx, I_a, I_b, kappa_a, kappa_s,
+    eta, nsteps and optionally vel, E, F (torch tensors on the GPU)."""
+    arr = (lbrt_domain * len(domains))()
+    f32 = _torch().float32
+    for k, dm in enumerate(domains):
+        ctx = dm["ctx"]
+        d = ctx.desc
+        n, nc, st = d.ndir, d.ncell, d.c.storage
+        arr[k].ctx = ctx.handle.value
+        arr[k].I_a = _ptr(dm["I_a"], f"domains[{k}].I_a", n * nc, _pop_dtype(st)).value
+        arr[k].I_b = _ptr(dm["I_b"], f"domains[{k}].I_b", n * nc, _pop_dtype(st)).value
+        arr[k].kappa_a = _ptr(dm["kappa_a"], "kappa_a", nc, f32).value
+        arr[k].kappa_s = _ptr(dm["kappa_s"], "kappa_s", nc, f32).value
+        arr[k].eta = _ptr(dm["eta"], "eta", nc, f32).value
+        v = _ptr(dm.get("vel"), "vel", 3 * nc, f32)
+        arr[k].vel = v.value if v is not None else None
+        arr[k].nsteps = int(dm["nsteps"])
+        e = _ptr(dm.get("E"), "E", nc, _moment_dtype(st))
+        fF = _ptr(dm.get("F"), "F", 3 * nc, _moment_dtype(st))
+        arr[k].E = e.value if e is not None else None
+        arr[k].F = fF.value if fF is not None else None
+    h = ctypes.c_void_p()
+    _check(_lib.lbrt_batch_create(arr, len(domains), ctypes.byref(h)))
+    return Batch(h.value, list(domains))
+
+
+def lbrt_step_batched(batch: Batch, stream=None) -> None:
+    _check(_lib.lbrt_step_batched(batch.handle, _stream(stream)))
+
+
+def lbrt_batch_error(batch: Batch) -> int:
+    """Nonzero if a queue wait of the last run hit its spin limit (synchronises)."""
+    flag = ctypes.c_int32(0)
+    _check(_lib.lbrt_batch_error(batch.handle, ctypes.byref(flag)))
+    return int(flag.value)
+
+
+def lbrt_batch_destroy(batch: Batch) -> None:
+    batch.close()
+
+
 def exported_symbols() -> list:
     """Names of the C entry points the binding wraps."""
     return ["lbrt_validate", "lbrt_init", "lbrt_destroy", "lbrt_step", "lbrt_moments",
-            "lbrt_convert", "lbrt_adjoint_step", "lbrt_last_error"]
+            "lbrt_convert", "lbrt_adjoint_step", "lbrt_set_tiling", "lbrt_batch_create",
+            "lbrt_step_batched", "lbrt_batch_error", "lbrt_batch_destroy", "lbrt_last_error"]
 
 
 def library():

@@ -66,6 +66,7 @@ struct lbrt_ctx {
   // General-kernel tile lists (device, int4 per block), for calls without
   // (index 0) and with (index 1) inflow ghost planes on a z face.
   int4 *general_dev[2] = {nullptr, nullptr};
+  std::vector<int4> general_host[2];
   int ngeneral[2] = {0, 0};
   int main_zr0[2] = {0, 0}, main_nzr[2] = {0, 0};
   int device = 0;
@@ -267,6 +268,7 @@ int plan_tiles(lbrt_ctx *c, int variant, bool zlo_inflow, bool zhi_inflow) {
     }
   }
   c->ngeneral[variant] = (int)list.size();
+  c->general_host[variant] = list;
   if (c->general_dev[variant]) (void)hipFree(c->general_dev[variant]);
   c->general_dev[variant] = nullptr;
   if (list.empty()) return LBRT_OK;
@@ -678,6 +680,193 @@ int lbrt_convert(lbrt_ctx *c, const void *src, int32_t src_storage, void *dst,
   hipError_t e = launch_convert(src, src_storage, dst, dst_storage, c->scales_dev, d.ndir, ncell,
                                 static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "lbrt_convert");
+  return LBRT_OK;
+}
+
+}  // extern "C"
+
+struct lbrt_batch {
+  int ndom = 0;
+  BatchKernel kernel{nullptr, 0};
+  int nblocks = 0;
+  BatchPlan plan{};
+  // device allocations
+  BatchDomain *dom = nullptr;
+  int4 *tiles = nullptr;
+  long long *tile_prefix = nullptr, *step_offset = nullptr;
+  int32_t *step_active = nullptr;
+  unsigned long long *next = nullptr, *done = nullptr;
+  unsigned int *error = nullptr;
+  InflowArgs *noinflow = nullptr;
+};
+
+extern "C" {
+
+int lbrt_set_tiling(lbrt_ctx *c, int32_t tx, int32_t ty, int32_t zlen, int32_t zlen_general) {
+  if (!c) return fail(LBRT_E_INVAL, "ctx is NULL");
+  if (tx <= 0 || ty <= 0 || tx * ty != kTileCells || (tx & (tx - 1)) != 0)
+    return fail(LBRT_E_INVAL, "tile %d x %d: need tx * ty = %d with tx a power of two", tx, ty,
+                (int)kTileCells);
+  if (zlen <= 0 || zlen_general <= 0) return fail(LBRT_E_INVAL, "z-range lengths must be > 0");
+  const lbrt_desc &d = c->desc;
+  c->tile = TileShape{tx, ty};
+  c->zlen = std::min(zlen, d.nz);
+  c->zlen_general = zlen_general;
+  int rc = plan_tiles(c, 0, false, false);
+  if (rc == LBRT_OK) {
+    const bool zlo = d.bc[LBRT_FACE_MZ] == LBRT_BC_INFLOW, zhi = d.bc[LBRT_FACE_PZ] == LBRT_BC_INFLOW;
+    rc = plan_tiles(c, 1, zlo, zhi);
+  }
+  if (rc != LBRT_OK) return rc;
+  KParams p = make_params(c);
+  return ensure_partials(c, total_partials(p));
+}
+
+void lbrt_batch_destroy(lbrt_batch *b) {
+  if (!b) return;
+  void *ptrs[] = {b->dom, b->tiles, b->tile_prefix, b->step_offset, b->step_active, b->next,
+                  b->done, b->error, b->noinflow};
+  for (void *q : ptrs)
+    if (q) (void)hipFree(q);
+  delete b;
+}
+
+int lbrt_batch_create(const lbrt_domain *domains, int32_t ndomains, lbrt_batch **out) {
+  if (!out) return fail(LBRT_E_INVAL, "out is NULL");
+  if (!domains || ndomains < 1) return fail(LBRT_E_INVAL, "need at least one domain");
+  const lbrt_ctx *c0 = domains[0].ctx;
+  if (!c0) return fail(LBRT_E_INVAL, "domains[0].ctx is NULL");
+  for (int k = 0; k < ndomains; ++k) {
+    const lbrt_domain &D = domains[k];
+    if (!D.ctx) return fail(LBRT_E_INVAL, "domains[%d].ctx is NULL", k);
+    const lbrt_desc &d = D.ctx->desc;
+    if (d.storage != c0->desc.storage || D.ctx->bucket != c0->bucket ||
+        d.moving_fluid != c0->desc.moving_fluid)
+      return fail(LBRT_E_INVAL, "domains[%d]: every domain needs the same storage, direction "
+                  "bucket and fluid kind", k);
+    if (!D.I_a || !D.I_b || D.I_a == D.I_b)
+      return fail(LBRT_E_INVAL, "domains[%d]: two distinct population buffers needed", k);
+    if (!D.kappa_a || !D.kappa_s || !D.eta)
+      return fail(LBRT_E_INVAL, "domains[%d]: kappa_a, kappa_s, eta required", k);
+    if ((d.moving_fluid != 0) != (D.vel != nullptr))
+      return fail(LBRT_E_INVAL, "domains[%d]: vel must be given iff the fluid moves", k);
+    if (D.nsteps < 0) return fail(LBRT_E_INVAL, "domains[%d].nsteps = %d < 0", k, D.nsteps);
+  }
+  BatchKernel bk = batch_kernel_for(c0->desc.storage, c0->bucket, c0->desc.moving_fluid != 0);
+  if (!bk.launch)
+    return fail(LBRT_E_UNSUPPORTED, "no batched kernel for storage %d with %d directions (%s)",
+                c0->desc.storage, c0->desc.ndir, c0->desc.moving_fluid ? "moving" : "static");
+  // order: longest run first, so that the domains active at any step are a prefix
+  std::vector<int> order(ndomains);
+  for (int k = 0; k < ndomains; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return domains[a].nsteps > domains[b].nsteps; });
+  std::vector<BatchDomain> dom(ndomains);
+  std::vector<int4> tiles;
+  std::vector<long long> prefix(ndomains + 1, 0);
+  std::vector<size_t> tile_start(ndomains);
+  for (int j = 0; j < ndomains; ++j) {
+    const lbrt_domain &D = domains[order[j]];
+    const lbrt_ctx *c = D.ctx;
+    KParams p = make_params(c);
+    tile_start[j] = tiles.size();
+    for (int zr = p.main_zr0; zr < p.main_zr0 + p.main_nzr; ++zr)
+      for (int ty = p.main_ty0; ty < p.main_ty0 + p.main_nty; ++ty)
+        for (int tx = 0; tx < p.ntx; ++tx) {
+          const int zb = zr * p.zlen;
+          tiles.push_back(make_int4(tx * p.tx, ty * p.ty, zb, std::min(p.nz, zb + p.zlen)));
+        }
+    for (const int4 &w : c->general_host[0]) tiles.push_back(make_int4(w.x, w.y, w.z, -w.w));
+    BatchDomain &B = dom[j];
+    B.p = p;
+    B.p.flags &= ~(uint32_t)(KF_DIAG | KF_WRITE_EF | KF_XGHOSTS);
+    B.tab = c->tab_dev;
+    B.I[0] = D.I_a;
+    B.I[1] = D.I_b;
+    B.ka = D.kappa_a;
+    B.ks = D.kappa_s;
+    B.eta = D.eta;
+    B.vel = D.vel;
+    B.E = D.E;
+    B.F = D.F;
+    B.ntiles = (int32_t)(tiles.size() - tile_start[j]);
+    B.nsteps = D.nsteps;
+    prefix[j + 1] = prefix[j] + B.ntiles;
+  }
+  const int maxsteps = domains[order[0]].nsteps;
+  std::vector<int32_t> active(std::max(maxsteps, 1), 0);
+  std::vector<long long> offset(maxsteps + 1, 0);
+  for (int st = 0; st < maxsteps; ++st) {
+    int a = 0;
+    while (a < ndomains && domains[order[a]].nsteps > st) ++a;
+    active[st] = a;
+    offset[st + 1] = offset[st] + prefix[a];
+  }
+  lbrt_batch *b = new lbrt_batch();
+  b->ndom = ndomains;
+  b->kernel = bk;
+  int dev = 0, ncu = 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      ncu <= 0)
+    ncu = 256;
+  b->nblocks = ncu * bk.blocks_per_cu;
+  hipError_t e = hipSuccess;
+  auto up = [&](void **dst, const void *src, size_t bytes) {
+    if (e != hipSuccess) return;
+    e = hipMalloc(dst, std::max<size_t>(bytes, 8));
+    if (e == hipSuccess && bytes) e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+  };
+  up((void **)&b->tiles, tiles.data(), sizeof(int4) * tiles.size());
+  for (int j = 0; j < ndomains; ++j) dom[j].tiles = b->tiles + tile_start[j];
+  up((void **)&b->dom, dom.data(), sizeof(BatchDomain) * dom.size());
+  up((void **)&b->tile_prefix, prefix.data(), sizeof(long long) * prefix.size());
+  up((void **)&b->step_offset, offset.data(), sizeof(long long) * offset.size());
+  up((void **)&b->step_active, active.data(), sizeof(int32_t) * active.size());
+  InflowArgs none;
+  std::memset(&none, 0, sizeof(none));
+  up((void **)&b->noinflow, &none, sizeof(none));
+  if (e == hipSuccess) e = hipMalloc(&b->next, sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMalloc(&b->done, sizeof(unsigned long long) * ndomains);
+  if (e == hipSuccess) e = hipMalloc(&b->error, sizeof(unsigned int));
+  if (e != hipSuccess) {
+    const int rc = fail(e == hipErrorOutOfMemory ? LBRT_E_NOMEM : LBRT_E_HIP,
+                        "lbrt_batch_create: %s", hipGetErrorString(e));
+    lbrt_batch_destroy(b);
+    return rc;
+  }
+  BatchPlan &bp = b->plan;
+  bp.dom = b->dom;
+  bp.tile_prefix = b->tile_prefix;
+  bp.step_offset = b->step_offset;
+  bp.step_active = b->step_active;
+  bp.maxsteps = maxsteps;
+  bp.total = offset[maxsteps];
+  bp.next = b->next;
+  bp.done = b->done;
+  bp.error = b->error;
+  bp.noinflow = b->noinflow;
+  *out = b;
+  return LBRT_OK;
+}
+
+int lbrt_step_batched(lbrt_batch *b, void *stream) {
+  if (!b) return fail(LBRT_E_INVAL, "batch is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_batch_reset(b->next, b->done, b->ndom, b->error, s);
+  if (e != hipSuccess) return hip_fail(e, "lbrt_step_batched: resetting the queue");
+  if (b->plan.total == 0) return LBRT_OK;
+  e = b->kernel.launch(b->plan, b->nblocks, s);
+  if (e != hipSuccess) return hip_fail(e, "lbrt_step_batched: launching the persistent kernel");
+  return LBRT_OK;
+}
+
+int lbrt_batch_error(lbrt_batch *b, int32_t *flag) {
+  if (!b || !flag) return fail(LBRT_E_INVAL, "batch and flag are required");
+  unsigned int v = 0;
+  hipError_t e = hipMemcpy(&v, b->error, sizeof(v), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "lbrt_batch_error");
+  *flag = (int32_t)v;
   return LBRT_OK;
 }
 

@@ -111,6 +111,46 @@ using StepLauncher = hipError_t (*)(const void *Iin, void *Iout, const float *ka
 
 StepLauncher step_launcher(int storage, int bucket_index, bool moving);
 
+// ---------------------------------------------------------------------------
+// Batched form (one persistent launch over many domains)
+// ---------------------------------------------------------------------------
+struct BatchDomain {
+  KParams p;              // the domain's parameters (no diagnostics)
+  const void *tab;        // its direction table (two copies of NB slots)
+  const void *I[2];       // ping-pong pair: step s reads I[s & 1]
+  const float *ka, *ks, *eta, *vel;
+  void *E, *F;            // moments after the last step, or null
+  const int4 *tiles;      // (x0, y0, zb, ze): ze > 0 main path, ze < 0 general (-ze)
+  int32_t ntiles;
+  int32_t nsteps;
+};
+
+struct BatchPlan {
+  const BatchDomain *dom;          // sorted by step count, longest first
+  const long long *tile_prefix;    // [ndom + 1]: items of the first k domains
+  const long long *step_offset;    // [maxsteps + 1]: queue index of step s's first item
+  const int32_t *step_active;      // [maxsteps]: domains active at step s (a prefix)
+  int32_t maxsteps;
+  long long total;                 // items in the queue
+  unsigned long long *next;        // queue head
+  unsigned long long *done;        // [ndom]: completed items per domain
+  unsigned int *error;             // nonzero: a wait hit its spin limit
+  const InflowArgs *noinflow;      // no ghost planes
+};
+
+// spin iterations (each a short sleep) before a wait gives up, ~seconds
+constexpr unsigned kBatchSpinLimit = 1u << 24;
+
+using BatchLauncher = hipError_t (*)(const BatchPlan &bp, int nblocks, hipStream_t s);
+struct BatchKernel {
+  BatchLauncher launch;
+  int blocks_per_cu;
+};
+// The batched kernel for (storage, bucket, fluid), or launch == nullptr.
+BatchKernel batch_kernel_for(int storage, int bucket_index, bool moving);
+hipError_t launch_batch_reset(unsigned long long *next, unsigned long long *done, int ndom,
+                              unsigned int *error, hipStream_t s);
+
 hipError_t launch_moments(int storage, const void *I, const void *tab, const KParams &p,
                           void *E, void *F, hipStream_t s);
 hipError_t launch_convert(const void *src, int src_storage, void *dst, int dst_storage,
