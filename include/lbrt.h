@@ -205,20 +205,18 @@ int lbrt_set_tiling(lbrt_ctx *ctx, int32_t tx, int32_t ty, int32_t zlen, int32_t
 
 /*
  * Batched form: many independent domains (each its own context, buffers,
- * fields and step count) advanced together by ONE persistent kernel launch.
- * Not in the paper.  A domain runs nsteps steps as lbrt_step would (result in
- * I_b when nsteps is odd), without diagnostics or inflow ghosts; E, F (or
- * NULL) receive its moments after the last step.  Every domain must share the
- * storage type, the direction bucket and the fluid kind of the first;
- * supported: FP32 storage, static fluid.
+ * fields and step count) advanced together.  Not in the paper.  A domain runs
+ * nsteps steps as lbrt_step would (result in I_b when nsteps is odd), without
+ * diagnostics or inflow ghosts; E, F (or NULL) receive its moments after the
+ * last step.  Every domain must share the storage type, the direction bucket
+ * and the fluid kind of the first; supported: FP32 storage, static fluid.
+ * Step s of the batch is one kernel launch over every tile of every domain
+ * still running at step s, so small domains fill the GPU together.
  *
- * lbrt_batch_create builds the work queue on the host and uploads it (call it
- * outside graph capture); it copies what it needs from the domains, whose
- * contexts and buffers must outlive the batch.  lbrt_step_batched only
- * enqueues kernels (a counter reset and the persistent launch) and may be
- * captured in a hipGraph and replayed.  lbrt_batch_error reports, after the
- * stream has finished (it synchronises), whether a queue wait exceeded its
- * spin limit (flag != 0: the results of that run are not to be trusted).
+ * lbrt_batch_create builds the tile lists on the host and uploads them (call
+ * it outside graph capture); the domains' contexts and buffers must outlive
+ * the batch.  lbrt_step_batched only enqueues kernels (one per step of the
+ * longest domain) and may be captured in a hipGraph and replayed as one.
  */
 typedef struct {
   lbrt_ctx *ctx;
@@ -232,7 +230,6 @@ typedef struct lbrt_batch lbrt_batch;
 
 int lbrt_batch_create(const lbrt_domain *domains, int32_t ndomains, lbrt_batch **out);
 int lbrt_step_batched(lbrt_batch *batch, void *stream);
-int lbrt_batch_error(lbrt_batch *batch, int32_t *flag);
 void lbrt_batch_destroy(lbrt_batch *batch);
 
 /* Message describing the last error returned on the calling thread

@@ -97,8 +97,6 @@ def _load():
     lib.lbrt_batch_create.restype = ctypes.c_int
     lib.lbrt_step_batched.argtypes = [vp, vp]
     lib.lbrt_step_batched.restype = ctypes.c_int
-    lib.lbrt_batch_error.argtypes = [vp, ctypes.POINTER(i32)]
-    lib.lbrt_batch_error.restype = ctypes.c_int
     lib.lbrt_batch_destroy.argtypes = [vp]
     lib.lbrt_batch_destroy.restype = None
     lib.lbrt_last_error.argtypes = []
@@ -367,13 +365,6 @@ def lbrt_step_batched(batch: Batch, stream=None) -> None:
     _check(_lib.lbrt_step_batched(batch.handle, _stream(stream)))
 
 
-def lbrt_batch_error(batch: Batch) -> int:
-    """Nonzero if a queue wait of the last run hit its spin limit (synchronises)."""
-    flag = ctypes.c_int32(0)
-    _check(_lib.lbrt_batch_error(batch.handle, ctypes.byref(flag)))
-    return int(flag.value)
-
-
 def lbrt_batch_destroy(batch: Batch) -> None:
     batch.close()
 
@@ -382,7 +373,7 @@ def exported_symbols() -> list:
     """Names of the C entry points the binding wraps."""
     return ["lbrt_validate", "lbrt_init", "lbrt_destroy", "lbrt_step", "lbrt_moments",
             "lbrt_convert", "lbrt_adjoint_step", "lbrt_set_tiling", "lbrt_batch_create",
-            "lbrt_step_batched", "lbrt_batch_error", "lbrt_batch_destroy", "lbrt_last_error"]
+            "lbrt_step_batched", "lbrt_batch_destroy", "lbrt_last_error"]
 
 
 def library():

@@ -130,14 +130,15 @@ void build_table(const lbrt_ctx &c, std::vector<DirTab<T>> &tab) {
   for (int k = 0; k < c.nb; ++k) {
     DirTab<T> &e = tab[k];
     std::memset(&e, 0, sizeof(e));
-    if (k >= d.ndir) {  // null direction: reads its own cell of plane order[0] with weight 0
+    if (k >= d.ndir) {
+      // null slot: reads in-box cells of plane order[0] with every weight 0,
+      // so its streamed value is 0 and it adds nothing to the moments; it is
+      // never stored (active = 0)
       e.plane = c.order[0];
       e.plane_el = (int64_t)e.plane * ncell;
       e.plane_off = (int64_t)e.plane * ncell * esize;
       e.scale = T(1);
       e.inv_scale = T(1);
-      e.wx[0] = e.wy[0] = T(1);
-      e.wz_new = T(1);
       continue;
     }
     const int i = c.order[k];
@@ -687,16 +688,14 @@ int lbrt_convert(lbrt_ctx *c, const void *src, int32_t src_storage, void *dst,
 
 struct lbrt_batch {
   int ndom = 0;
-  BatchKernel kernel{nullptr, 0};
-  int nblocks = 0;
+  BatchLauncher launch = nullptr;
   BatchPlan plan{};
+  std::vector<long long> step_items;   // blocks of each step's launch
   // device allocations
   BatchDomain *dom = nullptr;
   int4 *tiles = nullptr;
-  long long *tile_prefix = nullptr, *step_offset = nullptr;
+  long long *tile_prefix = nullptr;
   int32_t *step_active = nullptr;
-  unsigned long long *next = nullptr, *done = nullptr;
-  unsigned int *error = nullptr;
   InflowArgs *noinflow = nullptr;
 };
 
@@ -724,8 +723,7 @@ int lbrt_set_tiling(lbrt_ctx *c, int32_t tx, int32_t ty, int32_t zlen, int32_t z
 
 void lbrt_batch_destroy(lbrt_batch *b) {
   if (!b) return;
-  void *ptrs[] = {b->dom, b->tiles, b->tile_prefix, b->step_offset, b->step_active, b->next,
-                  b->done, b->error, b->noinflow};
+  void *ptrs[] = {b->dom, b->tiles, b->tile_prefix, b->step_active, b->noinflow};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   delete b;
@@ -752,8 +750,8 @@ int lbrt_batch_create(const lbrt_domain *domains, int32_t ndomains, lbrt_batch *
       return fail(LBRT_E_INVAL, "domains[%d]: vel must be given iff the fluid moves", k);
     if (D.nsteps < 0) return fail(LBRT_E_INVAL, "domains[%d].nsteps = %d < 0", k, D.nsteps);
   }
-  BatchKernel bk = batch_kernel_for(c0->desc.storage, c0->bucket, c0->desc.moving_fluid != 0);
-  if (!bk.launch)
+  BatchLauncher bl = batch_launcher(c0->desc.storage, c0->bucket, c0->desc.moving_fluid != 0);
+  if (!bl)
     return fail(LBRT_E_UNSUPPORTED, "no batched kernel for storage %d with %d directions (%s)",
                 c0->desc.storage, c0->desc.ndir, c0->desc.moving_fluid ? "moving" : "static");
   // order: longest run first, so that the domains active at any step are a prefix
@@ -795,22 +793,20 @@ int lbrt_batch_create(const lbrt_domain *domains, int32_t ndomains, lbrt_batch *
   }
   const int maxsteps = domains[order[0]].nsteps;
   std::vector<int32_t> active(std::max(maxsteps, 1), 0);
-  std::vector<long long> offset(maxsteps + 1, 0);
+  lbrt_batch *b = new lbrt_batch();
+  b->ndom = ndomains;
+  b->launch = bl;
+  b->step_items.assign(std::max(maxsteps, 0), 0);
   for (int st = 0; st < maxsteps; ++st) {
     int a = 0;
     while (a < ndomains && domains[order[a]].nsteps > st) ++a;
     active[st] = a;
-    offset[st + 1] = offset[st] + prefix[a];
+    b->step_items[st] = prefix[a];
+    if (prefix[a] > 0x7fffffffLL) {
+      delete b;
+      return fail(LBRT_E_INVAL, "step %d of the batch has %lld tiles (too many)", st, prefix[a]);
+    }
   }
-  lbrt_batch *b = new lbrt_batch();
-  b->ndom = ndomains;
-  b->kernel = bk;
-  int dev = 0, ncu = 0;
-  (void)hipGetDevice(&dev);
-  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      ncu <= 0)
-    ncu = 256;
-  b->nblocks = ncu * bk.blocks_per_cu;
   hipError_t e = hipSuccess;
   auto up = [&](void **dst, const void *src, size_t bytes) {
     if (e != hipSuccess) return;
@@ -821,14 +817,10 @@ int lbrt_batch_create(const lbrt_domain *domains, int32_t ndomains, lbrt_batch *
   for (int j = 0; j < ndomains; ++j) dom[j].tiles = b->tiles + tile_start[j];
   up((void **)&b->dom, dom.data(), sizeof(BatchDomain) * dom.size());
   up((void **)&b->tile_prefix, prefix.data(), sizeof(long long) * prefix.size());
-  up((void **)&b->step_offset, offset.data(), sizeof(long long) * offset.size());
   up((void **)&b->step_active, active.data(), sizeof(int32_t) * active.size());
   InflowArgs none;
   std::memset(&none, 0, sizeof(none));
   up((void **)&b->noinflow, &none, sizeof(none));
-  if (e == hipSuccess) e = hipMalloc(&b->next, sizeof(unsigned long long));
-  if (e == hipSuccess) e = hipMalloc(&b->done, sizeof(unsigned long long) * ndomains);
-  if (e == hipSuccess) e = hipMalloc(&b->error, sizeof(unsigned int));
   if (e != hipSuccess) {
     const int rc = fail(e == hipErrorOutOfMemory ? LBRT_E_NOMEM : LBRT_E_HIP,
                         "lbrt_batch_create: %s", hipGetErrorString(e));
@@ -838,13 +830,8 @@ int lbrt_batch_create(const lbrt_domain *domains, int32_t ndomains, lbrt_batch *
   BatchPlan &bp = b->plan;
   bp.dom = b->dom;
   bp.tile_prefix = b->tile_prefix;
-  bp.step_offset = b->step_offset;
   bp.step_active = b->step_active;
   bp.maxsteps = maxsteps;
-  bp.total = offset[maxsteps];
-  bp.next = b->next;
-  bp.done = b->done;
-  bp.error = b->error;
   bp.noinflow = b->noinflow;
   *out = b;
   return LBRT_OK;
@@ -852,21 +839,9 @@ int lbrt_batch_create(const lbrt_domain *domains, int32_t ndomains, lbrt_batch *
 
 int lbrt_step_batched(lbrt_batch *b, void *stream) {
   if (!b) return fail(LBRT_E_INVAL, "batch is NULL");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = launch_batch_reset(b->next, b->done, b->ndom, b->error, s);
-  if (e != hipSuccess) return hip_fail(e, "lbrt_step_batched: resetting the queue");
-  if (b->plan.total == 0) return LBRT_OK;
-  e = b->kernel.launch(b->plan, b->nblocks, s);
-  if (e != hipSuccess) return hip_fail(e, "lbrt_step_batched: launching the persistent kernel");
-  return LBRT_OK;
-}
-
-int lbrt_batch_error(lbrt_batch *b, int32_t *flag) {
-  if (!b || !flag) return fail(LBRT_E_INVAL, "batch and flag are required");
-  unsigned int v = 0;
-  hipError_t e = hipMemcpy(&v, b->error, sizeof(v), hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return hip_fail(e, "lbrt_batch_error");
-  *flag = (int32_t)v;
+  if (b->plan.maxsteps == 0) return LBRT_OK;
+  hipError_t e = b->launch(b->plan, b->step_items.data(), static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "lbrt_step_batched");
   return LBRT_OK;
 }
 

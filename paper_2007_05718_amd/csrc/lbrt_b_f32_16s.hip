@@ -1,8 +1,6 @@
-// Batched persistent kernel: float storage, 16-slot bucket, static fluid.
+// Batched step kernel: float storage, 16-slot bucket, static fluid.
 #include "lbrt_batch_kernel.h"
 
 namespace lbrt {
-BatchKernel batch_f32_16_static() {
-  return {&launch_batch<float, 16, false>, batch_blocks_per_cu<float, 16, false>()};
-}
+BatchLauncher batch_f32_16_static() { return &launch_batch<float, 16, false>; }
 }  // namespace lbrt

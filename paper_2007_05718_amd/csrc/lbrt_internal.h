@@ -127,29 +127,19 @@ struct BatchDomain {
 
 struct BatchPlan {
   const BatchDomain *dom;          // sorted by step count, longest first
-  const long long *tile_prefix;    // [ndom + 1]: items of the first k domains
-  const long long *step_offset;    // [maxsteps + 1]: queue index of step s's first item
+  const long long *tile_prefix;    // [ndom + 1]: tiles of the first k domains
   const int32_t *step_active;      // [maxsteps]: domains active at step s (a prefix)
   int32_t maxsteps;
-  long long total;                 // items in the queue
-  unsigned long long *next;        // queue head
-  unsigned long long *done;        // [ndom]: completed items per domain
-  unsigned int *error;             // nonzero: a wait hit its spin limit
   const InflowArgs *noinflow;      // no ghost planes
 };
 
-// spin iterations (each a short sleep) before a wait gives up, ~seconds
-constexpr unsigned kBatchSpinLimit = 1u << 24;
+// Launches steps [0, maxsteps) of a batch, one launch of step_items[s] blocks
+// per step (host array).
+using BatchLauncher = hipError_t (*)(const BatchPlan &bp, const long long *step_items,
+                                     hipStream_t s);
+// The batched kernel for (storage, bucket, fluid), or nullptr.
+BatchLauncher batch_launcher(int storage, int bucket_index, bool moving);
 
-using BatchLauncher = hipError_t (*)(const BatchPlan &bp, int nblocks, hipStream_t s);
-struct BatchKernel {
-  BatchLauncher launch;
-  int blocks_per_cu;
-};
-// The batched kernel for (storage, bucket, fluid), or launch == nullptr.
-BatchKernel batch_kernel_for(int storage, int bucket_index, bool moving);
-hipError_t launch_batch_reset(unsigned long long *next, unsigned long long *done, int ndom,
-                              unsigned int *error, hipStream_t s);
 
 hipError_t launch_moments(int storage, const void *I, const void *tab, const KParams &p,
                           void *E, void *F, hipStream_t s);

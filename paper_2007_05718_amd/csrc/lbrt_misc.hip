@@ -180,25 +180,6 @@ hipError_t launch_zface(int storage, const void *I, const void *tab, const KPara
   return hipGetLastError();
 }
 
-// Clears the batched queue's counters (a kernel, not a memset, so that a
-// captured graph replays it reliably).
-__global__ void batch_reset_kernel(unsigned long long *next, unsigned long long *done, int ndom,
-                                   unsigned int *error) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < ndom) done[i] = 0ull;
-  if (i == 0) {
-    *next = 0ull;
-    *error = 0u;
-  }
-}
-
-hipError_t launch_batch_reset(unsigned long long *next, unsigned long long *done, int ndom,
-                              unsigned int *error, hipStream_t s) {
-  hipLaunchKernelGGL(batch_reset_kernel, dim3((ndom + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
-                     next, done, ndom, error);
-  return hipGetLastError();
-}
-
 hipError_t launch_fill_f64(double *p, int n, double v, hipStream_t s) {
   hipLaunchKernelGGL(fill_f64_kernel, dim3((n + 63) / 64), dim3(64), 0, s, p, n, v);
   return hipGetLastError();

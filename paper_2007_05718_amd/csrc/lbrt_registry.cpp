@@ -70,22 +70,22 @@ StepLauncher step_launcher(int storage, int bucket_index, bool moving) {
   return nullptr;
 }
 
-BatchKernel batch_f32_16_static();
-BatchKernel batch_f32_32_static();
-BatchKernel batch_f32_56_static();
-BatchKernel batch_f32_112_static();
-BatchKernel batch_f32_152_static();
+BatchLauncher batch_f32_16_static();
+BatchLauncher batch_f32_32_static();
+BatchLauncher batch_f32_56_static();
+BatchLauncher batch_f32_112_static();
+BatchLauncher batch_f32_152_static();
 
 // Batched kernels exist for FP32 storage and a static fluid.
-BatchKernel batch_kernel_for(int storage, int bucket_index, bool moving) {
-  if (bucket_index < 0 || bucket_index >= kNumBuckets) return {nullptr, 0};
+BatchLauncher batch_launcher(int storage, int bucket_index, bool moving) {
+  if (bucket_index < 0 || bucket_index >= kNumBuckets) return nullptr;
   const int nb = kBuckets[bucket_index];
   if (storage == LBRT_FP32 && nb == 16 && !moving) return batch_f32_16_static();
   if (storage == LBRT_FP32 && nb == 32 && !moving) return batch_f32_32_static();
   if (storage == LBRT_FP32 && nb == 56 && !moving) return batch_f32_56_static();
   if (storage == LBRT_FP32 && nb == 112 && !moving) return batch_f32_112_static();
   if (storage == LBRT_FP32 && nb == 152 && !moving) return batch_f32_152_static();
-  return {nullptr, 0};
+  return nullptr;
 }
 
 }  // namespace lbrt

@@ -1,7 +1,8 @@
-"""GPU tests of the batched persistent form: domains of uneven size,
-opacity and step count in one launch give bit-for-bit the results of the
-same domains run one by one with lbrt_step, replay identically from a
-captured graph, and match the FP64 oracle on sampled domains."""
+"""GPU tests of the batched form: domains of uneven size, opacity and step
+count advanced together (one launch per step over all running domains) give
+bit-for-bit the results of the same domains run one by one with lbrt_step,
+replay identically from a captured graph, and match the FP64 oracle on
+sampled domains."""
 import numpy as np
 import pytest
 
@@ -51,7 +52,6 @@ def test_batched_equals_sequential_bitwise():
     b = L.lbrt_batch_create(doms)
     L.lbrt_step_batched(b)
     torch.cuda.synchronize()
-    assert L.lbrt_batch_error(b) == 0
     for p, dm in zip(probs, doms):
         Ia, Ib = dm["I0"].clone(), torch.zeros_like(dm["I0"])
         E = torch.zeros(p.ncell, device="cuda")
@@ -91,7 +91,6 @@ def test_batched_graph_replays_match_eager():
         torch.cuda.synchronize()
         g.replay()
         torch.cuda.synchronize()
-        assert L.lbrt_batch_error(b) == 0
         for dm, ref in zip(doms, eager):
             assert torch.equal(_result(dm), ref), rep
     b.close()
@@ -113,3 +112,11 @@ def test_batched_matches_oracle_on_sampled_domains():
         print(p.name, p.shape, p.steps, f"{err:.2e}", flush=True)
         assert err < 1e-5
     b.close()
+
+
+@pytest.mark.skip(reason="the single persistent launch (a step-major work queue with per-domain "
+                  "completion counters and spin waits) went silent in both of its GPU runs; "
+                  "its polling invalidated the L2 on every iteration.  It is switched off: the "
+                  "batched form runs one multi-domain launch per step instead")
+def test_persistent_single_launch_batched_kernel():
+    pass
