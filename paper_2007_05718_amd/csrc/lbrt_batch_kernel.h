@@ -15,7 +15,7 @@
 namespace lbrt {
 
 template <typename S, int NB, bool MOVING>
-__global__ void __launch_bounds__(kBlock) batch_kernel(const BatchPlan bp, int s) {
+__global__ void __launch_bounds__(64 * waves_for(NB)) batch_kernel(const BatchPlan bp, int s) {
   using T = typename StoreTraits<S>::T;
   // item within step s; XCD k takes the k-th contiguous run of items, so
   // neighbouring tiles of a domain share that XCD's L2
@@ -49,8 +49,8 @@ __global__ void __launch_bounds__(kBlock) batch_kernel(const BatchPlan bp, int s
 template <typename S, int NB, bool MOVING>
 hipError_t launch_batch(const BatchPlan &bp, const long long *step_items, hipStream_t st) {
   for (int s = 0; s < bp.maxsteps; ++s) {
-    hipLaunchKernelGGL((batch_kernel<S, NB, MOVING>), dim3((unsigned)step_items[s]), dim3(kBlock),
-                       0, st, bp, s);
+    hipLaunchKernelGGL((batch_kernel<S, NB, MOVING>), dim3((unsigned)step_items[s]),
+                       dim3(64 * waves_for(NB)), 0, st, bp, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -141,10 +141,10 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// Sum M per-thread values over the block; thread j < M writes out[j].
-template <int M>
+// Sum M per-thread values over a block of W waves; thread j < M writes out[j].
+template <int M, int W = kWaves>
 __device__ inline void block_sums(const double (&v)[M], double *out) {
-  __shared__ double red[kBlock / 64][M];
+  __shared__ double red[W][M];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int j = 0; j < M; ++j) {
@@ -155,8 +155,29 @@ __device__ inline void block_sums(const double (&v)[M], double *out) {
   if (threadIdx.x < M) {
     double s = 0.0;
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) s += red[w][threadIdx.x];
+    for (int w = 0; w < W; ++w) s += red[w][threadIdx.x];
     out[threadIdx.x] = s;
+  }
+}
+
+// Waves per block of the step kernels for a bucket of NB direction slots:
+// about 14 slots per wave keeps a lane's streamed and carried values in
+// registers without spilling.
+constexpr int waves_for(int nb) { return nb >= 112 ? 8 : 4; }
+// Blocks per CU the main kernel is compiled for (register budget): two
+// 8-wave blocks, so that one block computes while the other waits for HBM.
+constexpr int blocks_per_cu(int nb) { return nb >= 112 ? 2 : 3; }
+
+// Fixed-order pairwise sum of W per-wave values, ((v0 + v1) + (v2 + v3)) + ...
+template <typename T, int W>
+__device__ __forceinline__ T tree_sum(const T (&v)[W]) {
+  if constexpr (W == 1) {
+    return v[0];
+  } else {
+    T h[W / 2];
+#pragma unroll
+    for (int i = 0; i < W / 2; ++i) h[i] = v[2 * i] + v[2 * i + 1];
+    return tree_sum<T, W / 2>(h);
   }
 }
 
@@ -306,7 +327,7 @@ struct Acc {
   T Es = T(0), F0 = T(0), F1 = T(0), F2 = T(0);  // static (F0..F2) or moving (F0 = A, F1 = B)
 };
 
-template <bool MOVING, int J, typename T>
+template <bool MOVING, int J, int M, typename T>
 __device__ __forceinline__ void accumulate(Acc<T> &m, const DirTab<T> *__restrict__ tb,
                                            const T *Is, T vx, T vy, T vz, T dtWk) {
   if constexpr (MOVING) {
@@ -316,6 +337,13 @@ __device__ __forceinline__ void accumulate(Acc<T> &m, const DirTab<T> *__restric
     const T a = rcp<T>(fma(dtWk, D, T(1)));
     m.F0 = fma(D * D * a, Is[J], m.F0);
     m.F1 = fma(d.w * a, rcp<T>(D), m.F1);
+  } else if constexpr ((J & 1) == 0 && J == M - 1) {
+    // an unpaired last slot (an odd number of slots per wave)
+    const DirTab<T> &d = tb[J];
+    m.Es += Is[J];
+    m.F0 = fma(d.n[0], Is[J], m.F0);
+    m.F1 = fma(d.n[1], Is[J], m.F1);
+    m.F2 = fma(d.n[2], Is[J], m.F2);
   } else if constexpr ((J & 1) == 1) {
     const DirTab<T> &da = tb[J - 1], &db = tb[J];
     const T a = Is[J - 1], b = Is[J];
@@ -331,7 +359,7 @@ __device__ __forceinline__ void accumulate(Acc<T> &m, const DirTab<T> *__restric
 // The fused step.  NB direction slots (a multiple of 8, padded with null
 // directions); wave q owns slots [q NB/4, (q+1) NB/4).
 // ---------------------------------------------------------------------------
-template <typename S, int NB, bool MOVING, bool MAIN>
+template <typename S, int NB, bool MOVING, bool MAIN, int NW = waves_for(NB)>
 __device__ __forceinline__ void
 march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__ ka,
       const float *__restrict__ ks, const float *__restrict__ eta, const float *__restrict__ vel,
@@ -342,12 +370,12 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
   using Tr = StoreTraits<S>;
   using T = typename Tr::T;
   constexpr int SZ = (int)sizeof(S);
-  constexpr int M = NB / kWaves;
-  static_assert(NB % (2 * kWaves) == 0, "direction slots must split into pairs per wave");
+  constexpr int M = NB / NW;
+  static_assert(NB % NW == 0, "direction slots must split evenly over the waves");
 
   const int nx = p.nx, ny = p.ny, nz = p.nz;
   const int64_t pc = (int64_t)nx * ny;   // cells per z-plane
-  const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // direction quarter
+  const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // this wave's share
   const int lane = threadIdx.x & 63;
   const int perx = p.periodic[0], pery = p.periodic[1], perz = p.periodic[2];
 
@@ -462,14 +490,14 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
     unroll<0, M>(pro);
   }
 
-  __shared__ T red[2][kWaves][4][64];
-  T cur[4] = {T(0), T(0), T(0), T(0)};
+  __shared__ T red[2][NW][4][64];
   // element offsets of the new planes of output plane z: z (sz >= 0) and the
   // plane above (sz < 0), clamped into the box on a non-periodic axis
   auto plane_above = [&](int z) {
     const int za = z + 1 < nz ? z + 1 : (perz ? 0 : nz - 1);
     return (int64_t)za * pc;
   };
+  T cur[4] = {T(0), T(0), T(0), T(0)};
   if constexpr (MAIN)
     if (zb < ze) load4(tb[0], tb[0].dzn ? plane_above(zb) : (int64_t)zb * pc, cur);
 
@@ -505,10 +533,13 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
       // non-periodic z axis) is vacuum: its clamped loads get weight 0.
       const int64_t cz1 = plane_above(z);
       // the plane above a non-periodic box is vacuum: weight 0
-      const bool top_ghost = !perz && z + 1 >= nz;
+      const int gh = (!perz && z + 1 >= nz) ? 1 : 0;
+      // the plane above the last plane of the range belongs to the next block
+      const int lastz = z + 1 >= ze ? 1 : 0;
       // BOOK: also book the x-face outflux of the own values (x-face tiles
       // with diagnostics on; a block-uniform choice between two copies of
-      // the slot loop keeps the common one free of branches)
+      // the slot loop keeps the common one free of branches).  Each slot
+      // issues the next slot's loads before interpolating its own.
       auto slot = [&]<int J, bool BOOK>() {
         const DirTab<T> &d = tb[J];
         T nxt[4];
@@ -518,15 +549,17 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
         if constexpr (BOOK) {
           // the plane above the range belongs to the next block
           const T ko = fma(d.cxp, xop, d.cxm * xom);
-          const T dxs = (d.dzn && z + 1 >= ze) ? T(0) : d.dxs;
+          const T dxs = d.dxs * (T)(1 - (d.dzn & lastz));
           fx = fma(ko * dxs, cur[0], fx);
         }
-        const T wn = (d.dzn && top_ghost) ? T(0) : d.wz_new;
+        // (arithmetic, not a select: a select with a table load on one side
+        // becomes a branch that splits the slot loop into basic blocks)
+        const T wn = d.wz_new * (T)(1 - (d.dzn & gh));
         T sv = fma(d.wz_old, carry[J], wn * Pn);
         if (Tr::kReduced) sv *= d.scale;
         Is[J] = sv;
         carry[J] = Pn;
-        accumulate<MOVING, J>(m, tb, Is, vx, vy, vz, dtWk);
+        accumulate<MOVING, J, M>(m, tb, Is, vx, vy, vz, dtWk);
         if constexpr (J + 1 < M) {
 #pragma unroll
           for (int b = 0; b < 4; ++b) cur[b] = nxt[b];
@@ -546,7 +579,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
         if (Tr::kReduced) sv *= d.scale;
         Is[J] = valid ? sv : T(0);
         carry[J] = Pn;
-        accumulate<MOVING, J>(m, tb, Is, vx, vy, vz, dtWk);
+        accumulate<MOVING, J, M>(m, tb, Is, vx, vy, vz, dtWk);
       };
       unroll<0, M>(body);
     }
@@ -585,17 +618,21 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
       }
     }
 
-    // Combine the four waves' partial sums in a fixed order,
-    // (q0 + q1) + (q2 + q3), identical in every wave.
+    // Combine the waves' partial sums in a fixed pairwise order, identical
+    // in every wave.
     red[par][q][0][lane] = m.Es;
     red[par][q][1][lane] = m.F0;
     red[par][q][2][lane] = m.F1;
     red[par][q][3][lane] = m.F2;
     __syncthreads();
     auto comb = [&](int b, int j) {
-      return (red[b][0][j][lane] + red[b][1][j][lane]) + (red[b][2][j][lane] + red[b][3][j][lane]);
+      T v[NW];
+#pragma unroll
+      for (int w = 0; w < NW; ++w) v[w] = red[b][w][j][lane];
+      return tree_sum<T, NW>(v);
     };
     const T Es = comb(par, 0), S0 = comb(par, 1), S1 = comb(par, 2), S2 = comb(par, 3);
+
 
     // the next plane's first loads go out before the collision's stores
     if constexpr (MAIN)
@@ -748,7 +785,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
     v[6] = 0.0;
     v[7] = 0.0;
     v[8] = fin;
-    block_sums<kStepPartials>(v, partials + (int64_t)blockIdx.x * kStepPartials);
+    block_sums<kStepPartials, NW>(v, partials + (int64_t)blockIdx.x * kStepPartials);
   }
 }
 
@@ -756,7 +793,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
 // lanes, in z ranges whose z ghost planes (if any) are vacuum.  Block id ->
 // tile in the XCD-aware order of xcd_tile.
 template <typename S, int NB, bool MOVING>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(64 * waves_for(NB), blocks_per_cu(NB))
 step_kernel_main(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__ ka,
                  const float *__restrict__ ks, const float *__restrict__ eta,
                  const float *__restrict__ vel,
@@ -778,7 +815,7 @@ step_kernel_main(const S *__restrict__ Iin, S *__restrict__ Iout, const float *_
 // next to an inflow z face), in short z ranges, from a host-built list of
 // (x0, y0, zb, ze).  Its partials follow the main kernel's.
 template <typename S, int NB, bool MOVING>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(64 * waves_for(NB))
 step_kernel_general(const S *__restrict__ Iin, S *__restrict__ Iout,
                     const float *__restrict__ ka, const float *__restrict__ ks,
                     const float *__restrict__ eta, const float *__restrict__ vel,
@@ -849,12 +886,14 @@ hipError_t launch_step(const void *Iin, void *Iout, const float *ka, const float
   using T = typename StoreTraits<S>::T;
   // the general kernel first: its short blocks do not leave a tail
   if (p.ngeneral > 0)
-    hipLaunchKernelGGL((step_kernel_general<S, NB, MOVING>), dim3(p.ngeneral), dim3(kBlock), 0,
+    hipLaunchKernelGGL((step_kernel_general<S, NB, MOVING>), dim3(p.ngeneral),
+                       dim3(64 * waves_for(NB)), 0,
                        s, static_cast<const S *>(Iin), static_cast<S *>(Iout), ka, ks, eta, vel,
                        static_cast<const DirTab<T> *>(tab), p, inflow, static_cast<T *>(E),
                        static_cast<T *>(F), partials);
   if (p.nblocks > 0)
-    hipLaunchKernelGGL((step_kernel_main<S, NB, MOVING>), dim3(p.nblocks), dim3(kBlock), 0, s,
+    hipLaunchKernelGGL((step_kernel_main<S, NB, MOVING>), dim3(p.nblocks),
+                       dim3(64 * waves_for(NB)), 0, s,
                        static_cast<const S *>(Iin), static_cast<S *>(Iout), ka, ks, eta, vel,
                        static_cast<const DirTab<T> *>(tab), p, inflow, static_cast<T *>(E),
                        static_cast<T *>(F), partials);
