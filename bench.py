@@ -9,8 +9,13 @@ then timed with BF16 and FP16 population storage.
 
 Prints ONE JSON line.  `value` is cell-direction updates per second (GDUPS)
 of the FP32 form with all inputs resident in HBM.  The roofline entry is
-for the fused step kernel: algorithmic bytes per launch over the kernel's
-mean duration, timed with HIP events on the stream the kernel runs on.
+for the fused step (its main and boundary kernels, one lbrt_step call
+without diagnostics): algorithmic bytes per call over the call's mean
+duration, timed with HIP events on the stream the kernels run on.
+Further forms on the same GPU: BF16 and FP16 storage of the same workload,
+the batched sweep of 512 uneven domains (one multi-domain launch per step,
+against the same domains run one by one), and the moving-fluid run with its
+adjoint (forward steps and the checkpointed reverse sweep).
 The CPU baseline is the FP64 oracle (test infrastructure) timed on a bounded
 sample of the same workload on this host.
 """
@@ -19,6 +24,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import re
 import os
 import sys
 import time
@@ -149,6 +155,81 @@ def copy_ceiling_gbs(torch, nbytes: int = 4 << 30, reps: int = 10) -> float:
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def time_batched(L, torch, ndomains=512, seed=4):
+    """The batched opacity sweep: one lbrt_step_batched call against the same
+    domains advanced one by one with lbrt_step.  Returns a dict."""
+    import workloads as wl
+    probs = [wl.batch_domain(d, seed=seed) for d in range(ndomains)]
+    f = lambda v, n: torch.full((n,), float(v), dtype=torch.float32, device="cuda")
+    doms = []
+    updates = 0
+    for p in probs:
+        ctx = L.lbrt_init(L.Desc.from_problem(p, storage=L.LBRT_FP32))
+        n = p.ndir * p.ncell
+        doms.append(dict(ctx=ctx, I_a=torch.zeros(n, device="cuda"),
+                         I_b=torch.zeros(n, device="cuda"),
+                         kappa_a=f(p.meta["kappa_a"], p.ncell),
+                         kappa_s=f(p.meta["kappa_s"], p.ncell),
+                         eta=f(p.meta["kappa_a"], p.ncell), nsteps=p.steps))
+        updates += n * p.steps
+    b = L.lbrt_batch_create(doms)
+    stream = torch.cuda.current_stream()
+    L.lbrt_step_batched(b)          # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    L.lbrt_step_batched(b)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_batch = e0.elapsed_time(e1) * 1e-3
+    e0.record(stream)
+    for dm in doms:
+        L.lbrt_step(dm["ctx"], dm["I_a"], dm["I_b"], dm["kappa_a"], dm["kappa_s"], dm["eta"],
+                    nsteps=dm["nsteps"])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_seq = e0.elapsed_time(e1) * 1e-3
+    b.close()
+    for dm in doms:
+        dm["ctx"].close()
+    return {"domains": ndomains, "updates": updates,
+            "GDUPS": round(updates / t_batch / 1e9, 2), "seconds": round(t_batch, 3),
+            "sequential_GDUPS": round(updates / t_seq / 1e9, 2),
+            "sequential_seconds": round(t_seq, 3),
+            "speedup_vs_sequential": round(t_seq / t_batch, 3)}
+
+
+def time_adjoint(L, torch, n=192, steps=64, K=8):
+    """The moving-fluid workload: steps forward FP32 steps, then the gradient of
+    the energy leaving through +x with respect to kappa_a (eta = kappa_a)."""
+    import workloads as wl
+    from paper_2007_05718_amd import autodiff
+    p = wl.moving(n=n, steps=steps, alloc_state=False)
+    ctx = L.lbrt_init(L.Desc.from_problem(p, storage=L.LBRT_FP32))
+    f = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).reshape(-1).cuda()
+    ka = f(p.kappa_a).requires_grad_(True)
+    ks, vel = f(p.kappa_s), f(p.vel)
+    I0 = torch.zeros(p.ndir * p.ncell, device="cuda")
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record(stream)
+    Lval = autodiff.detected_energy(ctx, I0, ka, ks, ka * 1.0, steps, face=1,
+                                    checkpoint_every=K, vel=vel)
+    ev[1].record(stream)
+    Lval.backward()
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    tf = ev[0].elapsed_time(ev[1]) * 1e-3
+    tb = ev[1].elapsed_time(ev[2]) * 1e-3
+    updates = p.ndir * p.ncell * steps
+    out = {"cells": p.ncell, "directions": p.ndir, "steps": steps, "checkpoint_every": K,
+           "L": float(Lval.item()), "forward_seconds": round(tf, 3),
+           "forward_GDUPS": round(updates / tf / 1e9, 2), "backward_seconds": round(tb, 3),
+           "grad_norm": float(ka.grad.norm().item())}
+    ctx.close()
+    return out
+
+
 def cpu_baseline(prob, planes: int = 16):
     """FP64 oracle, one step on a slab of `planes` z-planes of the workload."""
     import copy
@@ -176,18 +257,20 @@ def cpu_baseline(prob, planes: int = 16):
 
 
 def traffic_entry(ndir, ncell):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "step_kernel_beams256_fp32_traffic.json")
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled) from the
+    committed rocprofv3 counter summary, if it was taken on the current
+    kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "step_kernel_beams256_fp32_traffic.md")
     if not os.path.exists(path):
         return None
-    try:
-        d = json.load(open(path))
-    except Exception:
+    kv = {}
+    for line in open(path):
+        m = re.match(r"^([a-z_]+): (\S+)$", line.strip())
+        if m:
+            kv[m.group(1)] = m.group(2)
+    if kv.get("kernel_source_digest") != kernel_source_digest():
         return None
-    if d.get("kernel_source_digest") != kernel_source_digest():
-        return None
-    return d.get("bytes_per_launch")
+    return float(kv["bytes_per_launch"]) if "bytes_per_launch" in kv else None
 
 
 def main():
@@ -197,7 +280,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=256, help="grid edge (default 256)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
-    ap.add_argument("--forms", default="bf16,fp16", help="extra storage forms to time")
+    ap.add_argument("--forms", default="bf16,fp16,batched,adjoint",
+                    help="extra forms to time (bf16, fp16, batched, adjoint)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -223,18 +307,32 @@ def main():
     achieved = bytes_launch / (kms * 1e-3) / 1e9
     forms = {}
     for name in [s for s in args.forms.split(",") if s]:
-        st = {"bf16": L.LBRT_BF16, "fp16": L.LBRT_FP16}[name]
-        log(f"timing {name}")
-        w2, c2, _ = time_form(L, torch, prob, st, args.steps, args.warmup)
-        k2 = kernel_only_ms(L, torch, prob, st, args.steps)
-        b2 = algorithmic_bytes_per_cell(ndir, 2) * ncell
-        forms[name] = {
-            "GDUPS": round(updates / (w2 * 1e-3) / 1e9, 2),
-            "ms_per_step": round(w2, 4),
-            "kernel_ms": round(k2, 4),
-            "hbm_GBs_algorithmic": round(b2 / (k2 * 1e-3) / 1e9, 1),
-            "speedup_vs_fp32": round(wall / w2, 3),
-        }
+        if name in ("bf16", "fp16"):
+            st = {"bf16": L.LBRT_BF16, "fp16": L.LBRT_FP16}[name]
+            log(f"timing {name}")
+            w2, c2, _ = time_form(L, torch, prob, st, args.steps, args.warmup)
+            k2 = kernel_only_ms(L, torch, prob, st, args.steps)
+            b2 = algorithmic_bytes_per_cell(ndir, 2) * ncell
+            forms[name] = {
+                "GDUPS": round(updates / (w2 * 1e-3) / 1e9, 2),
+                "ms_per_step": round(w2, 4),
+                "kernel_ms": round(k2, 4),
+                "hbm_GBs_algorithmic": round(b2 / (k2 * 1e-3) / 1e9, 1),
+                "speedup_vs_fp32": round(wall / w2, 3),
+            }
+        elif name == "batched":
+            log("timing the batched sweep (512 domains)")
+            try:
+                forms["batched_sweep_512"] = time_batched(L, torch)
+            except Exception as exc:   # report, keep the headline line
+                forms["batched_sweep_512"] = {"error": repr(exc)}
+        elif name == "adjoint":
+            log("timing the moving-fluid run and its adjoint")
+            try:
+                forms["moving_adjoint_192"] = time_adjoint(L, torch)
+            except Exception as exc:
+                forms["moving_adjoint_192"] = {"error": repr(exc)}
+        torch.cuda.empty_cache()
     log("copy ceiling")
     copy_gbs = copy_ceiling_gbs(torch)
     cpu = None
@@ -270,7 +368,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": tr,
-            "kernel": "step_kernel<float,110>",
+            "kernel": "step_kernel_main<float,112> + step_kernel_general<float,112>",
             "kernel_ms": round(kms, 4),
             "bytes_per_launch_algorithmic": bytes_launch,
             "copy_kernel_GBs": round(copy_gbs, 1),
