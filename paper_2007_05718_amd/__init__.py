@@ -18,7 +18,9 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lib", "liblbrt.so")
+# LBRT_LIBRARY names another build of the same library (e.g. one compiled
+# with different tuning macros); the default is the in-tree build.
+LIB_PATH = os.environ.get("LBRT_LIBRARY") or os.path.join(_HERE, "_lib", "liblbrt.so")
 
 LBRT_OK, LBRT_E_INVAL, LBRT_E_CFL, LBRT_E_QUAD = 0, -1, -2, -3
 LBRT_E_NOMEM, LBRT_E_HIP, LBRT_E_UNSUPPORTED = -4, -5, -6

@@ -164,9 +164,29 @@ __device__ inline void block_sums(const double (&v)[M], double *out) {
 // about 14 slots per wave keeps a lane's streamed and carried values in
 // registers without spilling.
 constexpr int waves_for(int nb) { return nb >= 112 ? 8 : 4; }
-// Blocks per CU the main kernel is compiled for (register budget): two
-// 8-wave blocks, so that one block computes while the other waits for HBM.
-constexpr int blocks_per_cu(int nb) { return nb >= 112 ? 2 : 3; }
+// Waves per SIMD the main kernel is compiled for: the second argument of
+// __launch_bounds__ is the minimum number of waves per execution unit (SIMD),
+// which caps VGPRs at 512 / that.  Two 8-wave blocks per CU (4 waves per SIMD,
+// 128 VGPRs) so that one block computes while the other waits for HBM; three
+// 4-wave blocks (3 per SIMD) for the smaller buckets.  16-bit storage asks
+// for 2: under the 128-VGPR cap the compiler packs two loaded 16-bit values
+// per VGPR, which waits for every prefetched load as soon as it is issued;
+// with the looser bound it still allocates under 128 VGPRs, unpacked.
+template <typename S>
+constexpr int waves_per_simd(int nb) { return sizeof(S) == 2 ? (nb >= 112 ? 2 : 3) : (nb >= 112 ? 4 : 3); }
+// Main path: slots whose four taps are in flight ahead of the slot being
+// interpolated, for M slots per wave (memory-level parallelism per wave;
+// each costs 4 VGPRs: 4 ahead fit the 128-VGPR budget at M = 14, 3 at 19).
+// FP64 taps take two VGPRs each, so FP64 keeps 2 slots ahead.
+#ifdef LBRT_PF_DEPTH
+template <typename S>
+constexpr int pf_depth(int m) { return m < LBRT_PF_DEPTH ? m : LBRT_PF_DEPTH; }
+#else
+template <typename S>
+constexpr int pf_depth(int m) {
+  return sizeof(S) == 8 ? (m < 2 ? m : 2) : (m <= 14 ? (m < 4 ? m : 4) : 3);
+}
+#endif
 
 // Fixed-order pairwise sum of W per-wave values, ((v0 + v1) + (v2 + v3)) + ...
 template <typename T, int W>
@@ -497,9 +517,18 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
     const int za = z + 1 < nz ? z + 1 : (perz ? 0 : nz - 1);
     return (int64_t)za * pc;
   };
-  T cur[4] = {T(0), T(0), T(0), T(0)};
+  // Main path: the taps of slots [J, J + D) of the plane are in flight
+  // while slot J is interpolated; the first D of the next plane go out
+  // before the collision's stores.
+  constexpr int D = pf_depth<S>(M);
+  T pf[M][4];
+  auto issue_first = [&](int zn) {
+    const int64_t czn = (int64_t)zn * pc, czn1 = plane_above(zn);
+    auto one = [&]<int J>() { load4(tb[J], tb[J].dzn ? czn1 : czn, pf[J]); };
+    unroll<0, D>(one);
+  };
   if constexpr (MAIN)
-    if (zb < ze) load4(tb[0], tb[0].dzn ? plane_above(zb) : (int64_t)zb * pc, cur);
+    if (zb < ze) issue_first(zb);
 
   for (int z = zb; z < ze; ++z) {
     const int par = (z - zb) & 1;
@@ -528,7 +557,6 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
     T Is[M];
     Acc<T> m;
     if constexpr (MAIN) {
-      // Each slot issues the next slot's loads before interpolating its own.
       // A new plane above the box (sz < 0 on the last plane of a
       // non-periodic z axis) is vacuum: its clamped loads get weight 0.
       const int64_t cz1 = plane_above(z);
@@ -538,12 +566,12 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
       const int lastz = z + 1 >= ze ? 1 : 0;
       // BOOK: also book the x-face outflux of the own values (x-face tiles
       // with diagnostics on; a block-uniform choice between two copies of
-      // the slot loop keeps the common one free of branches).  Each slot
-      // issues the next slot's loads before interpolating its own.
+      // the slot loop keeps the common one free of branches).  Slot J issues
+      // the loads of slot J + D before interpolating its own.
       auto slot = [&]<int J, bool BOOK>() {
         const DirTab<T> &d = tb[J];
-        T nxt[4];
-        if constexpr (J + 1 < M) load4(tb[J + 1], tb[J + 1].dzn ? cz1 : cz, nxt);
+        if constexpr (J + D < M) load4(tb[J + D], tb[J + D].dzn ? cz1 : cz, pf[J + D]);
+        const T(&cur)[4] = pf[J];
         const T k1 = xkeep(d);
         const T Pn = interp4(d, cur[0], cur[1] * k1, cur[2], cur[3] * k1);
         if constexpr (BOOK) {
@@ -560,10 +588,6 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
         Is[J] = sv;
         carry[J] = Pn;
         accumulate<MOVING, J, M>(m, tb, Is, vx, vy, vz, dtWk);
-        if constexpr (J + 1 < M) {
-#pragma unroll
-          for (int b = 0; b < 4; ++b) cur[b] = nxt[b];
-        }
       };
       auto body_book = [&]<int J>() { slot.template operator()<J, true>(); };
       auto body = [&]<int J>() { slot.template operator()<J, false>(); };
@@ -636,7 +660,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
 
     // the next plane's first loads go out before the collision's stores
     if constexpr (MAIN)
-      if (z + 1 < ze) load4(tb[0], tb[0].dzn ? plane_above(z + 1) : cz + pc, cur);
+      if (z + 1 < ze) issue_first(z + 1);
 
     S *const outz = Iout + cz;
     // The collision reads the other copy of the table, so that its loads are
@@ -793,7 +817,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
 // lanes, in z ranges whose z ghost planes (if any) are vacuum.  Block id ->
 // tile in the XCD-aware order of xcd_tile.
 template <typename S, int NB, bool MOVING>
-__global__ void __launch_bounds__(64 * waves_for(NB), blocks_per_cu(NB))
+__global__ void __launch_bounds__(64 * waves_for(NB), waves_per_simd<S>(NB))
 step_kernel_main(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__ ka,
                  const float *__restrict__ ks, const float *__restrict__ eta,
                  const float *__restrict__ vel,
