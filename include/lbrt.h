@@ -203,6 +203,12 @@ int lbrt_convert(lbrt_ctx *ctx, const void *src, int32_t src_storage,
  */
 int lbrt_set_tiling(lbrt_ctx *ctx, int32_t tx, int32_t ty, int32_t zlen, int32_t zlen_general);
 
+/* The context's current tiling (the defaults chosen by lbrt_init from the grid
+ * shape, or the last lbrt_set_tiling).  Any output pointer may be NULL.
+ * Errors: LBRT_E_INVAL when ctx is NULL. */
+int lbrt_get_tiling(const lbrt_ctx *ctx, int32_t *tx, int32_t *ty, int32_t *zlen,
+                    int32_t *zlen_general);
+
 /*
  * Batched form: many independent domains (each its own context, buffers,
  * fields and step count) advanced together.  Not in the paper.  A domain runs

@@ -95,6 +95,9 @@ def _load():
     lib.lbrt_adjoint_step.restype = ctypes.c_int
     lib.lbrt_set_tiling.argtypes = [vp, i32, i32, i32, i32]
     lib.lbrt_set_tiling.restype = ctypes.c_int
+    pi32 = ctypes.POINTER(i32)
+    lib.lbrt_get_tiling.argtypes = [vp, pi32, pi32, pi32, pi32]
+    lib.lbrt_get_tiling.restype = ctypes.c_int
     lib.lbrt_batch_create.argtypes = [ctypes.POINTER(lbrt_domain), i32, ctypes.POINTER(vp)]
     lib.lbrt_batch_create.restype = ctypes.c_int
     lib.lbrt_step_batched.argtypes = [vp, vp]
@@ -317,6 +320,13 @@ def lbrt_set_tiling(ctx: Context, tx: int, ty: int, zlen: int, zlen_general: int
     _check(_lib.lbrt_set_tiling(ctx.handle, int(tx), int(ty), int(zlen), int(zlen_general)))
 
 
+def lbrt_get_tiling(ctx: Context):
+    """The context's current (tx, ty, zlen, zlen_general)."""
+    v = [ctypes.c_int32() for _ in range(4)]
+    _check(_lib.lbrt_get_tiling(ctx.handle, *[ctypes.byref(x) for x in v]))
+    return tuple(int(x.value) for x in v)
+
+
 class Batch:
     """Owns an ``lbrt_batch`` plan and keeps its domains' tensors alive."""
 
@@ -374,8 +384,8 @@ def lbrt_batch_destroy(batch: Batch) -> None:
 def exported_symbols() -> list:
     """Names of the C entry points the binding wraps."""
     return ["lbrt_validate", "lbrt_init", "lbrt_destroy", "lbrt_step", "lbrt_moments",
-            "lbrt_convert", "lbrt_adjoint_step", "lbrt_set_tiling", "lbrt_batch_create",
-            "lbrt_step_batched", "lbrt_batch_destroy", "lbrt_last_error"]
+            "lbrt_convert", "lbrt_adjoint_step", "lbrt_set_tiling", "lbrt_get_tiling",
+            "lbrt_batch_create", "lbrt_step_batched", "lbrt_batch_destroy", "lbrt_last_error"]
 
 
 def library():

@@ -722,6 +722,16 @@ int lbrt_set_tiling(lbrt_ctx *c, int32_t tx, int32_t ty, int32_t zlen, int32_t z
   return ensure_partials(c, total_partials(p));
 }
 
+int lbrt_get_tiling(const lbrt_ctx *c, int32_t *tx, int32_t *ty, int32_t *zlen,
+                    int32_t *zlen_general) {
+  if (!c) return fail(LBRT_E_INVAL, "ctx is NULL");
+  if (tx) *tx = c->tile.tx;
+  if (ty) *ty = c->tile.ty;
+  if (zlen) *zlen = c->zlen;
+  if (zlen_general) *zlen_general = c->zlen_general;
+  return LBRT_OK;
+}
+
 void lbrt_batch_destroy(lbrt_batch *b) {
   if (!b) return;
   void *ptrs[] = {b->dom, b->tiles, b->tile_prefix, b->step_active, b->noinflow};
