@@ -101,6 +101,27 @@ template <typename T> __device__ inline T rcp(T x);
 template <> __device__ inline float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 template <> __device__ inline double rcp<double>(double x) { return 1.0 / x; }
 
+// a / b: FP32 by the hardware reciprocal and one Newton correction of the
+// quotient (within one ulp of the rounded quotient), FP64 exactly rounded.
+template <typename T> __device__ inline T div_fast(T a, T b);
+template <> __device__ inline float div_fast<float>(float a, float b) {
+  const float r = __builtin_amdgcn_rcpf(b);
+  const float q = a * r;
+  return fmaf(fmaf(-b, q, a), r, q);
+}
+template <> __device__ inline double div_fast<double>(double a, double b) { return a / b; }
+
+// v, or +0 when `zero` is 1: a mask on the bits (wave-uniform operands stay
+// scalar instructions; an arithmetic factor would be a vector conversion and
+// multiply, a select with a table load on one side a branch).
+template <typename T> __device__ __forceinline__ T zero_if(T v, int zero);
+template <> __device__ __forceinline__ float zero_if<float>(float v, int zero) {
+  return __uint_as_float(__float_as_uint(v) & ((uint32_t)zero - 1u));
+}
+template <> __device__ __forceinline__ double zero_if<double>(double v, int zero) {
+  return __longlong_as_double(__double_as_longlong(v) & ((long long)zero - 1));
+}
+
 // Unrolled loop helper: calls f.template operator()<J>() for J = 0..N-1.
 template <int J, int N, typename F>
 __device__ __forceinline__ void unroll(F &f) {
@@ -357,21 +378,12 @@ __device__ __forceinline__ void accumulate(Acc<T> &m, const DirTab<T> *__restric
     const T a = rcp<T>(fma(dtWk, D, T(1)));
     m.F0 = fma(D * D * a, Is[J], m.F0);
     m.F1 = fma(d.w * a, rcp<T>(D), m.F1);
-  } else if constexpr ((J & 1) == 0 && J == M - 1) {
-    // an unpaired last slot (an odd number of slots per wave)
+  } else {
     const DirTab<T> &d = tb[J];
     m.Es += Is[J];
     m.F0 = fma(d.n[0], Is[J], m.F0);
     m.F1 = fma(d.n[1], Is[J], m.F1);
     m.F2 = fma(d.n[2], Is[J], m.F2);
-  } else if constexpr ((J & 1) == 1) {
-    const DirTab<T> &da = tb[J - 1], &db = tb[J];
-    const T a = Is[J - 1], b = Is[J];
-    m.Es += a + b;
-    const T dd = a - b;
-    m.F0 = fma(da.n[0], dd, fma(da.n[0] + db.n[0], b, m.F0));
-    m.F1 = fma(da.n[1], dd, fma(da.n[1] + db.n[1], b, m.F1));
-    m.F2 = fma(da.n[2], dd, fma(da.n[2] + db.n[2], b, m.F2));
   }
 }
 
@@ -577,12 +589,11 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
         if constexpr (BOOK) {
           // the plane above the range belongs to the next block
           const T ko = fma(d.cxp, xop, d.cxm * xom);
-          const T dxs = d.dxs * (T)(1 - (d.dzn & lastz));
+          const T dxs = zero_if(d.dxs, d.dzn & lastz);
           fx = fma(ko * dxs, cur[0], fx);
         }
-        // (arithmetic, not a select: a select with a table load on one side
-        // becomes a branch that splits the slot loop into basic blocks)
-        const T wn = d.wz_new * (T)(1 - (d.dzn & gh));
+        // the new plane above a non-periodic box is vacuum
+        const T wn = zero_if(d.wz_new, d.dzn & gh);
         T sv = fma(d.wz_old, carry[J], wn * Pn);
         if (Tr::kReduced) sv *= d.scale;
         Is[J] = sv;
@@ -672,6 +683,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
       const T F0 = S0, F1 = S1, F2 = S2;
       // Collision: every mode becomes I_i = c I*_i + w_i (alpha + n_i . beta).
       const T lam = (T)p.lam;
+      const T third = T(1) / T(3);
       T c, alpha, be0, be1, be2;
       if (p.mode == LBRT_COLL_EXPLICIT) {
         // eq. (collision-step) with I^eq and S of eq. (source-and-equil)
@@ -680,13 +692,13 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
         const T g = dt * kst * lam;
         be0 = g * F0; be1 = g * F1; be2 = g * F2;
         En = c * Es + alpha;
-        Fn0 = c * F0 + be0 / T(3); Fn1 = c * F1 + be1 / T(3); Fn2 = c * F2 + be2 / T(3);
+        Fn0 = fma(be0, third, c * F0); Fn1 = fma(be1, third, c * F1); Fn2 = fma(be2, third, c * F2);
       } else if (p.mode == LBRT_COLL_LAMBDA) {
         // Lambda iteration: (E, F) <- moments of the decoupled solution,
         // which the rule's identities reduce to a scalar recursion per cell.
-        c = T(1) / (T(1) + dt * (kst + kat));
+        c = div_fast(T(1), T(1) + dt * (kst + kat));
         T Ek = Es, G0 = F0, G1 = F1, G2 = F2;
-        const T h = dt * kst * lam / T(3);
+        const T h = dt * kst * lam * third;
         for (int it = 1; it < p.lambda_iters; ++it) {
           Ek = c * (Es + dt * (kst * Ek + et));
           G0 = c * (F0 + h * G0); G1 = c * (F1 + h * G1); G2 = c * (F2 + h * G2);
@@ -695,14 +707,14 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
         const T g = c * dt * kst * lam;
         be0 = g * G0; be1 = g * G1; be2 = g * G2;
         En = c * Es + alpha;
-        Fn0 = c * F0 + be0 / T(3); Fn1 = c * F1 + be1 / T(3); Fn2 = c * F2 + be2 / T(3);
+        Fn0 = fma(be0, third, c * F0); Fn1 = fma(be1, third, c * F1); Fn2 = fma(be2, third, c * F2);
       } else {
         // eq. (rte_implicit) solved exactly: the moment equations decouple to
         // E = (E* + dt eta)/(1 + dt ka), F = F*/(1 + dt(k0 + ka) - dt k0 lam/3).
         const T den = T(1) + dt * (kst + kat);
-        c = T(1) / den;
-        En = (Es + dt * et) / (T(1) + dt * kat);
-        const T gF = T(1) / (den - dt * kst * lam / T(3));
+        c = div_fast(T(1), den);
+        En = div_fast(Es + dt * et, T(1) + dt * kat);
+        const T gF = div_fast(T(1), den - dt * kst * lam * third);
         Fn0 = F0 * gF; Fn1 = F1 * gF; Fn2 = F2 * gF;
         alpha = c * dt * (kst * En + et);
         const T g = c * dt * kst * lam;
@@ -742,8 +754,8 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
       //   I_i = a_i [I*_i + dt w_i (eta + k0 J) / (W^3 D_i^3)].
       const T A = S0 * (W * W);
       const T B = S1 * (dt / W);
-      const T J = (A + et * B) / (T(1) - kst * B);
-      const T gam = dt * (et + kst * J) / (W * W * W);
+      const T J = div_fast(A + et * B, T(1) - kst * B);
+      const T gam = div_fast(dt * (et + kst * J), W * W * W);
       T e = T(0), f0 = T(0), f1 = T(0), f2 = T(0);
       if (valid) {
 #pragma unroll
