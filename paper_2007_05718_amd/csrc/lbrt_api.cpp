@@ -52,6 +52,7 @@ struct lbrt_ctx {
   bool paired = false;
   std::vector<int> order;         // processing index -> storage plane
   void *tab_dev = nullptr;        // DirTab<float> or DirTab<double>, nb entries
+  size_t tab_bytes = 0;
   void *tab_moments_dev = nullptr;
   double *scales_dev = nullptr;   // per storage plane
   double *partials = nullptr;     // per-block sums of the step kernel
@@ -213,8 +214,9 @@ KParams make_params(const lbrt_ctx *c) {
   p.txlog = 0;
   while ((1 << p.txlog) < p.tx) ++p.txlog;
   p.zlen = c->zlen;
-  // main kernel: full x tiles, y tiles whose halo rows are inside the box
-  p.ntx = d.nx / p.tx;
+  // main kernel: every x tile (a ragged last tile masks its extra lanes), y
+  // tiles whose halo rows are inside the box
+  p.ntx = (d.nx + p.tx - 1) / p.tx;
   p.nty = (d.ny + p.ty - 1) / p.ty;
   p.main_ty0 = 1;
   p.main_nty = std::max(0, (d.ny - 1 - p.ty) / p.ty);
@@ -243,13 +245,13 @@ KParams make_params(const lbrt_ctx *c) {
 int plan_tiles(lbrt_ctx *c, int variant, bool zlo_inflow, bool zhi_inflow) {
   const lbrt_desc &d = c->desc;
   const int tx = c->tile.tx, ty = c->tile.ty;
-  const int ntx_full = d.nx / tx, ntx_all = (d.nx + tx - 1) / tx;
+  const int ntx_all = (d.nx + tx - 1) / tx;
   const int nty = (d.ny + ty - 1) / ty;
   const int main_nty = std::max(0, (d.ny - 1 - ty) / ty);
   const int nzr = (d.nz + c->zlen - 1) / c->zlen;
   int zr0 = zlo_inflow ? 1 : 0;
   int zr1 = nzr - (zhi_inflow ? 1 : 0);
-  if (zr1 < zr0 || ntx_full == 0 || main_nty == 0) zr1 = zr0;
+  if (zr1 < zr0 || main_nty == 0) zr1 = zr0;
   c->main_zr0[variant] = zr0;
   c->main_nzr[variant] = zr1 - zr0;
   const bool any_main = zr1 > zr0;
@@ -260,7 +262,7 @@ int plan_tiles(lbrt_ctx *c, int variant, bool zlo_inflow, bool zhi_inflow) {
   };
   for (int tiy = 0; tiy < nty; ++tiy) {
     for (int tix = 0; tix < ntx_all; ++tix) {
-      const bool main_xy = any_main && tix < ntx_full && tiy >= 1 && tiy <= main_nty;
+      const bool main_xy = any_main && tiy >= 1 && tiy <= main_nty;
       if (!main_xy) {
         add_column(tix, tiy, 0, d.nz);
       } else {
@@ -485,12 +487,14 @@ int lbrt_init(const lbrt_desc *d, lbrt_ctx **out) {
     std::vector<DirTab<double>> tab;
     build_table(*c, tab);
     tab_bytes = sizeof(DirTab<double>) * tab.size();
+    c->tab_bytes = tab_bytes;
     e = hipMalloc(&c->tab_dev, tab_bytes);
     if (e == hipSuccess) e = hipMemcpy(c->tab_dev, tab.data(), tab_bytes, hipMemcpyHostToDevice);
   } else {
     std::vector<DirTab<float>> tab;
     build_table(*c, tab);
     tab_bytes = sizeof(DirTab<float>) * tab.size();
+    c->tab_bytes = tab_bytes;
     e = hipMalloc(&c->tab_dev, tab_bytes);
     if (e == hipSuccess) e = hipMemcpy(c->tab_dev, tab.data(), tab_bytes, hipMemcpyHostToDevice);
   }
@@ -691,11 +695,12 @@ struct lbrt_batch {
   int ndom = 0;
   BatchLauncher launch = nullptr;
   BatchPlan plan{};
-  std::vector<long long> step_items;   // blocks of each step's launch
+  std::vector<long long> step_main, step_gen;   // blocks of each step's two launches
   // device allocations
   BatchDomain *dom = nullptr;
   int4 *tiles = nullptr;
-  long long *tile_prefix = nullptr;
+  long long *main_prefix = nullptr, *gen_prefix = nullptr;
+  char *tabs = nullptr;
   int32_t *step_active = nullptr;
   InflowArgs *noinflow = nullptr;
 };
@@ -734,7 +739,8 @@ int lbrt_get_tiling(const lbrt_ctx *c, int32_t *tx, int32_t *ty, int32_t *zlen,
 
 void lbrt_batch_destroy(lbrt_batch *b) {
   if (!b) return;
-  void *ptrs[] = {b->dom, b->tiles, b->tile_prefix, b->step_active, b->noinflow};
+  void *ptrs[] = {b->dom, b->tiles, b->tabs, b->main_prefix, b->gen_prefix, b->step_active,
+                  b->noinflow};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   delete b;
@@ -772,8 +778,9 @@ int lbrt_batch_create(const lbrt_domain *domains, int32_t ndomains, lbrt_batch *
                    [&](int a, int b) { return domains[a].nsteps > domains[b].nsteps; });
   std::vector<BatchDomain> dom(ndomains);
   std::vector<int4> tiles;
-  std::vector<long long> prefix(ndomains + 1, 0);
-  std::vector<size_t> tile_start(ndomains);
+  std::vector<long long> mprefix(ndomains + 1, 0), gprefix(ndomains + 1, 0);
+  std::vector<size_t> tile_start(ndomains), tab_start(ndomains);
+  size_t tab_total = 0;
   for (int j = 0; j < ndomains; ++j) {
     const lbrt_domain &D = domains[order[j]];
     const lbrt_ctx *c = D.ctx;
@@ -785,37 +792,36 @@ int lbrt_batch_create(const lbrt_domain *domains, int32_t ndomains, lbrt_batch *
           const int zb = zr * p.zlen;
           tiles.push_back(make_int4(tx * p.tx, ty * p.ty, zb, std::min(p.nz, zb + p.zlen)));
         }
-    for (const int4 &w : c->general_host[0]) tiles.push_back(make_int4(w.x, w.y, w.z, -w.w));
+    const int32_t nmain = (int32_t)(tiles.size() - tile_start[j]);
+    for (const int4 &w : c->general_host[0]) tiles.push_back(w);
     BatchDomain &B = dom[j];
     B.p = p;
     B.p.flags &= ~(uint32_t)(KF_DIAG | KF_WRITE_EF | KF_XGHOSTS);
-    B.tab = c->tab_dev;
-    B.I[0] = D.I_a;
-    B.I[1] = D.I_b;
-    B.ka = D.kappa_a;
-    B.ks = D.kappa_s;
-    B.eta = D.eta;
-    B.vel = D.vel;
-    B.E = D.E;
-    B.F = D.F;
+    tab_start[j] = tab_total;
+    tab_total += (c->tab_bytes + 255) / 256 * 256;
     B.ntiles = (int32_t)(tiles.size() - tile_start[j]);
+    B.nmain = nmain;
     B.nsteps = D.nsteps;
-    prefix[j + 1] = prefix[j] + B.ntiles;
+    mprefix[j + 1] = mprefix[j] + nmain;
+    gprefix[j + 1] = gprefix[j] + (B.ntiles - nmain);
   }
   const int maxsteps = domains[order[0]].nsteps;
   std::vector<int32_t> active(std::max(maxsteps, 1), 0);
   lbrt_batch *b = new lbrt_batch();
   b->ndom = ndomains;
   b->launch = bl;
-  b->step_items.assign(std::max(maxsteps, 0), 0);
+  b->step_main.assign(std::max(maxsteps, 0), 0);
+  b->step_gen.assign(std::max(maxsteps, 0), 0);
   for (int st = 0; st < maxsteps; ++st) {
     int a = 0;
     while (a < ndomains && domains[order[a]].nsteps > st) ++a;
     active[st] = a;
-    b->step_items[st] = prefix[a];
-    if (prefix[a] > 0x7fffffffLL) {
+    b->step_main[st] = mprefix[a];
+    b->step_gen[st] = gprefix[a];
+    if (mprefix[a] > 0x7fffffffLL || gprefix[a] > 0x7fffffffLL) {
       delete b;
-      return fail(LBRT_E_INVAL, "step %d of the batch has %lld tiles (too many)", st, prefix[a]);
+      return fail(LBRT_E_INVAL, "step %d of the batch has %lld + %lld tiles (too many)", st,
+                  mprefix[a], gprefix[a]);
     }
   }
   hipError_t e = hipSuccess;
@@ -825,9 +831,37 @@ int lbrt_batch_create(const lbrt_domain *domains, int32_t ndomains, lbrt_batch *
     if (e == hipSuccess && bytes) e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
   };
   up((void **)&b->tiles, tiles.data(), sizeof(int4) * tiles.size());
-  for (int j = 0; j < ndomains; ++j) dom[j].tiles = b->tiles + tile_start[j];
-  up((void **)&b->dom, dom.data(), sizeof(BatchDomain) * dom.size());
-  up((void **)&b->tile_prefix, prefix.data(), sizeof(long long) * prefix.size());
+  // the domains' direction tables, one block
+  if (e == hipSuccess) e = hipMalloc((void **)&b->tabs, std::max<size_t>(tab_total, 256));
+  for (int j = 0; j < ndomains && e == hipSuccess; ++j) {
+    const lbrt_ctx *c = domains[order[j]].ctx;
+    e = hipMemcpy(b->tabs + tab_start[j], c->tab_dev, c->tab_bytes, hipMemcpyDeviceToDevice);
+  }
+  // buffer offsets are taken from the domain array's own device address
+  if (e == hipSuccess) e = hipMalloc((void **)&b->dom, sizeof(BatchDomain) * dom.size());
+  if (e == hipSuccess) {
+    const char *g = reinterpret_cast<const char *>(b->dom);
+    auto off = [&](const void *ptr) -> int64_t {
+      return ptr ? (int64_t)(reinterpret_cast<const char *>(ptr) - g) : kNoBuffer;
+    };
+    for (int j = 0; j < ndomains; ++j) {
+      const lbrt_domain &D = domains[order[j]];
+      BatchDomain &B = dom[j];
+      B.tiles = b->tiles + tile_start[j];
+      B.tab = (int64_t)tab_start[j];
+      B.I[0] = off(D.I_a);
+      B.I[1] = off(D.I_b);
+      B.ka = off(D.kappa_a);
+      B.ks = off(D.kappa_s);
+      B.eta = off(D.eta);
+      B.vel = off(D.vel);
+      B.E = off(D.E);
+      B.F = off(D.F);
+    }
+    e = hipMemcpy(b->dom, dom.data(), sizeof(BatchDomain) * dom.size(), hipMemcpyHostToDevice);
+  }
+  up((void **)&b->main_prefix, mprefix.data(), sizeof(long long) * mprefix.size());
+  up((void **)&b->gen_prefix, gprefix.data(), sizeof(long long) * gprefix.size());
   up((void **)&b->step_active, active.data(), sizeof(int32_t) * active.size());
   InflowArgs none;
   std::memset(&none, 0, sizeof(none));
@@ -840,10 +874,13 @@ int lbrt_batch_create(const lbrt_domain *domains, int32_t ndomains, lbrt_batch *
   }
   BatchPlan &bp = b->plan;
   bp.dom = b->dom;
-  bp.tile_prefix = b->tile_prefix;
+  bp.main_prefix = b->main_prefix;
+  bp.gen_prefix = b->gen_prefix;
   bp.step_active = b->step_active;
   bp.maxsteps = maxsteps;
   bp.noinflow = b->noinflow;
+  bp.tabs = b->tabs;
+  bp.gbase = reinterpret_cast<char *>(b->dom);
   *out = b;
   return LBRT_OK;
 }
@@ -851,7 +888,8 @@ int lbrt_batch_create(const lbrt_domain *domains, int32_t ndomains, lbrt_batch *
 int lbrt_step_batched(lbrt_batch *b, void *stream) {
   if (!b) return fail(LBRT_E_INVAL, "batch is NULL");
   if (b->plan.maxsteps == 0) return LBRT_OK;
-  hipError_t e = b->launch(b->plan, b->step_items.data(), static_cast<hipStream_t>(stream));
+  hipError_t e = b->launch(b->plan, b->step_main.data(), b->step_gen.data(),
+                           static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "lbrt_step_batched");
   return LBRT_OK;
 }

@@ -114,29 +114,40 @@ StepLauncher step_launcher(int storage, int bucket_index, bool moving);
 // ---------------------------------------------------------------------------
 // Batched form (one persistent launch over many domains)
 // ---------------------------------------------------------------------------
+// Buffers of a batch domain are byte offsets from the batch's global base
+// pointer (a kernel argument), and its direction table an offset into the
+// batch's table block (a read-only kernel argument): pointers read from
+// device memory would make the compiler fall back to flat accesses and
+// per-lane table loads.
+constexpr int64_t kNoBuffer = INT64_MIN;
 struct BatchDomain {
   KParams p;              // the domain's parameters (no diagnostics)
-  const void *tab;        // its direction table (two copies of NB slots)
-  const void *I[2];       // ping-pong pair: step s reads I[s & 1]
-  const float *ka, *ks, *eta, *vel;
-  void *E, *F;            // moments after the last step, or null
-  const int4 *tiles;      // (x0, y0, zb, ze): ze > 0 main path, ze < 0 general (-ze)
-  int32_t ntiles;
+  int64_t tab;            // its direction table: byte offset into the table block
+  int64_t I[2];           // ping-pong pair: step s reads I[s & 1]
+  int64_t ka, ks, eta, vel;
+  int64_t E, F;           // moments after the last step, or kNoBuffer
+  const int4 *tiles;      // (x0, y0, zb, ze): the nmain main-path tiles, then the
+                          // general-path ones
+  int32_t ntiles, nmain;
   int32_t nsteps;
 };
 
 struct BatchPlan {
   const BatchDomain *dom;          // sorted by step count, longest first
-  const long long *tile_prefix;    // [ndom + 1]: tiles of the first k domains
+  const long long *main_prefix;    // [ndom + 1]: main-path tiles of the first k domains
+  const long long *gen_prefix;     // [ndom + 1]: general-path tiles of the first k domains
   const int32_t *step_active;      // [maxsteps]: domains active at step s (a prefix)
   int32_t maxsteps;
   const InflowArgs *noinflow;      // no ghost planes
+  const char *tabs;                // the domains' direction tables
+  char *gbase;                     // base of the domains' buffer offsets
 };
 
-// Launches steps [0, maxsteps) of a batch, one launch of step_items[s] blocks
-// per step (host array).
-using BatchLauncher = hipError_t (*)(const BatchPlan &bp, const long long *step_items,
-                                     hipStream_t s);
+// Launches steps [0, maxsteps) of a batch: per step, one launch of
+// step_gen[s] general-path blocks and one of step_main[s] main-path blocks
+// (host arrays).
+using BatchLauncher = hipError_t (*)(const BatchPlan &bp, const long long *step_main,
+                                     const long long *step_gen, hipStream_t s);
 // The batched kernel for (storage, bucket, fluid), or nullptr.
 BatchLauncher batch_launcher(int storage, int bucket_index, bool moving);
 

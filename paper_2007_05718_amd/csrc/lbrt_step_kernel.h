@@ -418,11 +418,15 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
   // for sx > 0 / sx < 0; on a face lane the wrapped cell (periodic) or the
   // lane's own cell (a vacuum/inflow ghost: zeroed).  All offsets stay inside
   // the plane.
-  const uint32_t o0 = valid ? (uint32_t)(x + nx * y) * (uint32_t)SZ : 0u;
+  // A ragged lane (x >= nx; main tiles are full in y) reads its row's last
+  // cell, so that every tap it loads stays inside the box; its values are
+  // never stored or summed.  General tiles send invalid lanes to cell 0.
+  const uint32_t o0 = valid ? (uint32_t)(x + nx * y) * (uint32_t)SZ
+                            : (MAIN ? (uint32_t)((nx - 1) + nx * y) * (uint32_t)SZ : 0u);
   const bool at0 = valid && x == 0, at1 = valid && x == nx - 1;
   uint32_t oxp = at0 ? (perx ? o0 + (uint32_t)((nx - 1) * SZ) : o0) : o0 - (uint32_t)SZ;
   uint32_t oxm = at1 ? (perx ? o0 - (uint32_t)((nx - 1) * SZ) : o0) : o0 + (uint32_t)SZ;
-  if (!valid) oxp = oxm = 0u;
+  if (!valid) oxp = oxm = o0;
   const bool lox = at0 && !perx, hix = at1 && !perx;   // on a non-periodic x face
   const bool loy = valid && y == 0 && !pery, hiy = valid && y == ny - 1 && !pery;
   // Main path, per lane: 1 where the x-shifted tap of a direction with
