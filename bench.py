@@ -155,9 +155,10 @@ def copy_ceiling_gbs(torch, nbytes: int = 4 << 30, reps: int = 10) -> float:
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def time_batched(L, torch, ndomains=512, seed=4):
+def time_batched(L, torch, ndomains=512, seed=4, sequential=True):
     """The batched opacity sweep: one lbrt_step_batched call against the same
-    domains advanced one by one with lbrt_step.  Returns a dict."""
+    domains advanced one by one with lbrt_step (unless sequential=False).
+    Returns a dict."""
     import workloads as wl
     probs = [wl.batch_domain(d, seed=seed) for d in range(ndomains)]
     f = lambda v, n: torch.full((n,), float(v), dtype=torch.float32, device="cuda")
@@ -182,21 +183,25 @@ def time_batched(L, torch, ndomains=512, seed=4):
     e1.record(stream)
     torch.cuda.synchronize()
     t_batch = e0.elapsed_time(e1) * 1e-3
-    e0.record(stream)
-    for dm in doms:
-        L.lbrt_step(dm["ctx"], dm["I_a"], dm["I_b"], dm["kappa_a"], dm["kappa_s"], dm["eta"],
-                    nsteps=dm["nsteps"])
-    e1.record(stream)
-    torch.cuda.synchronize()
-    t_seq = e0.elapsed_time(e1) * 1e-3
+    out = {"domains": ndomains, "updates": updates,
+           "GDUPS": round(updates / t_batch / 1e9, 2), "seconds": round(t_batch, 3),
+           "hbm_GBs_algorithmic": round(updates * algorithmic_bytes_per_cell(50, 4) / 50
+                                        / t_batch / 1e9, 1)}
+    if sequential:
+        e0.record(stream)
+        for dm in doms:
+            L.lbrt_step(dm["ctx"], dm["I_a"], dm["I_b"], dm["kappa_a"], dm["kappa_s"],
+                        dm["eta"], nsteps=dm["nsteps"])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_seq = e0.elapsed_time(e1) * 1e-3
+        out.update({"sequential_GDUPS": round(updates / t_seq / 1e9, 2),
+                    "sequential_seconds": round(t_seq, 3),
+                    "speedup_vs_sequential": round(t_seq / t_batch, 3)})
     b.close()
     for dm in doms:
         dm["ctx"].close()
-    return {"domains": ndomains, "updates": updates,
-            "GDUPS": round(updates / t_batch / 1e9, 2), "seconds": round(t_batch, 3),
-            "sequential_GDUPS": round(updates / t_seq / 1e9, 2),
-            "sequential_seconds": round(t_seq, 3),
-            "speedup_vs_sequential": round(t_seq / t_batch, 3)}
+    return out
 
 
 def time_adjoint(L, torch, n=192, steps=64, K=8):
@@ -282,6 +287,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--forms", default="bf16,fp16,batched,adjoint",
                     help="extra forms to time (bf16, fp16, batched, adjoint)")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="batched form: skip the one-domain-at-a-time comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -323,7 +330,8 @@ def main():
         elif name == "batched":
             log("timing the batched sweep (512 domains)")
             try:
-                forms["batched_sweep_512"] = time_batched(L, torch)
+                forms["batched_sweep_512"] = time_batched(
+                    L, torch, sequential=not args.no_sequential)
             except Exception as exc:   # report, keep the headline line
                 forms["batched_sweep_512"] = {"error": repr(exc)}
         elif name == "adjoint":
