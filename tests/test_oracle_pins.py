@@ -514,3 +514,23 @@ def test_detected_energy_gradient_matches_finite_differences(moving, bc, planes)
             fld[cell] = base
             fd = (Lp - Lm) / (2 * h)
             assert abs(fd - g[cell]) < 1e-6 * gmax + 1e-6 * abs(fd), (cell, fd, g[cell])
+
+
+@pytest.mark.parametrize("moving,bc,planes,coll", [
+    (False, (wl.BC_OUTFLOW,) * 6, 0, wl.COLL_IMPLICIT),
+    (False, (wl.BC_INFLOW, wl.BC_OUTFLOW, wl.BC_INFLOW, wl.BC_PERIODIC, wl.BC_PERIODIC,
+             wl.BC_PERIODIC), 4, wl.COLL_EXPLICIT),
+    (True, (wl.BC_PERIODIC,) * 2 + (wl.BC_OUTFLOW,) * 2 + (wl.BC_INFLOW,) * 2, 3,
+     wl.COLL_IMPLICIT),
+])
+def test_step_cells_equals_the_full_step(moving, bc, planes, coll):
+    """The sampled-cell step (used where a full oracle step is too large)
+    gives, at every cell including faces, edges and corners, the values of
+    the pinned full step: streaming is a pull, and the collision is local."""
+    p = wl.random_problem(17, shape=(5, 6, 7), npoints=26, bc=bc, inflow_planes=planes,
+                          moving_fluid=moving, collision=coll, steps=1)
+    full = orc.step(np.asarray(p.I0, dtype=np.float64), p)
+    cells = np.array(list(itertools.product(range(5), range(6), range(7))))
+    got = orc.step_cells(np.asarray(p.I0, dtype=np.float64), p, cells)
+    ref = full[:, cells[:, 0], cells[:, 1], cells[:, 2]]
+    assert np.allclose(got, ref, rtol=1e-13, atol=1e-300)
