@@ -23,29 +23,53 @@
 //   dJ/dks = (dA + eta dB + J (ks dB + B)) / (1 - ks B),
 //   dA = -dt W^3 sum D_i^3 a_i^2 I*_i,  dB = -dt^2 sum w_i a_i^2.
 //
-// Two kernels: adj_collide (one thread per cell, runtime loops over the
-// directions; the nu buffer first holds I* between its passes) and
-// adj_transpose (one thread per population).  This is the backward sweep,
-// run once per forward step of a differentiated run; it is written for
-// clarity and coalesced access, not fused like the forward step.
+// Three launches: adj_pull<false> computes I* = S I into the nu buffer (the
+// forward pull with its boundary rules); adj_collide (one thread per cell,
+// two passes over the directions) turns it into nu and adds the gradients;
+// adj_pull<true> computes lambda = d + S^T nu.  S^T is the same pull with
+// the shift signs reversed and no ghosts (a source outside the box gets
+// nothing back).  The pulls march one direction per block through z with
+// the separable form of the trilinear weights, like the forward step, so a
+// plane costs four row loads per direction instead of eight gathers.
 #include "lbrt_step_kernel.h"
 
 namespace lbrt {
 namespace {
 
-// I*_i at cell (x, y, z): the 8-tap pull with the forward step's boundary
-// rules (periodic wrap; a point outside along exactly one axis takes that
-// face's inflow ghost value for the slot, if any; vacuum otherwise).
-template <typename T>
-__device__ T pull8(const T *__restrict__ I, const DirTab<T> &d, const float *const *ghost,
-                   int x, int y, int z, const KParams &p) {
+constexpr int kPullRows = 4;    // rows (waves) per block of adj_pull
+constexpr int kPullZlen = 32;   // z planes marched per block
+
+// One direction per block (blockIdx.y, processing order), a 64 x kPullRows
+// tile of cells per block, marched through kPullZlen planes.  REV = false:
+// out = S in (the forward pull: periodic wrap; a tap outside the box along
+// exactly one axis takes that face's inflow ghost value, if any, else 0).
+// REV = true: out = d + S^T in (shift signs reversed, taps outside give 0,
+// d = the detector weights of `face` on its cells, face < 0 for none).
+template <typename T, bool REV>
+__global__ void __launch_bounds__(64 * kPullRows)
+adj_pull_kernel(const T *__restrict__ in, T *__restrict__ out, const DirTab<T> *__restrict__ tab,
+                const KParams p, const InflowArgs *__restrict__ inflow, int face) {
+  const int k = blockIdx.y;
+  const DirTab<T> &d = tab[k];
+  const int ntx = (p.nx + 63) >> 6, nty = (p.ny + kPullRows - 1) / kPullRows;
+  const int bx = blockIdx.x % ntx, r = blockIdx.x / ntx;
+  const int by = r % nty, bz = r / nty;
+  const int x = bx * 64 + (threadIdx.x & 63);
+  const int y = by * kPullRows + (threadIdx.x >> 6);
+  const int zb = bz * kPullZlen, ze = min(p.nz, zb + kPullZlen);
+  if (x >= p.nx || y >= p.ny) return;
+  const int sg = REV ? -1 : 1;
+  const int sx = sg * d.s[0], sy = sg * d.s[1], sz = sg * d.s[2];
   const int n3[3] = {p.nx, p.ny, p.nz};
-  T acc = T(0);
-  for (int b = 0; b < 8; ++b) {
-    const T wt = d.tw[b];
-    if (wt == T(0)) continue;
-    int c[3] = {x - (b & 1) * d.s[0], y - ((b >> 1) & 1) * d.s[1], z - (b >> 2) * d.s[2]};
-    int nout = 0, oa = -1;
+  const float *const *ghost = REV ? nullptr : inflow->ghost[k];
+  const int64_t pc = (int64_t)p.nx * p.ny;
+  const T *src = in + d.plane_el;
+
+  // value of the tap (cx, cy, cz) by the boundary rules
+  auto tap = [&](int cx, int cy, int cz) -> T {
+    int c[3] = {cx, cy, cz};
+    int nout = 0, oa = 0;
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
       if (p.periodic[a]) c[a] = wrap(c[a], n3[a]);
       if ((unsigned)c[a] >= (unsigned)n3[a]) {
@@ -53,34 +77,70 @@ __device__ T pull8(const T *__restrict__ I, const DirTab<T> &d, const float *con
         oa = a;
       }
     }
-    T v = T(0);
-    if (nout == 0) {
-      v = I[d.plane_el + ((int64_t)c[2] * p.ny + c[1]) * p.nx + c[0]];
-    } else if (nout == 1 && ghost[oa] != nullptr) {
-      // face layouts: x faces [z][y], y faces [z][x], z faces [y][x]
-      const int64_t gi = oa == 0 ? (int64_t)c[2] * p.ny + c[1]
-                                 : (oa == 1 ? (int64_t)c[2] * p.nx + c[0]
-                                            : (int64_t)c[1] * p.nx + c[0]);
-      v = (T)ghost[oa][gi];
-    }
-    acc = fma(wt, v, acc);
+    if (nout == 0) return src[(int64_t)c[2] * pc + (int64_t)c[1] * p.nx + c[0]];
+    if (REV || nout > 1 || ghost[oa] == nullptr) return T(0);
+    // face layouts: x faces [z][y], y faces [z][x], z faces [y][x]
+    const int64_t gi = oa == 0 ? (int64_t)c[2] * p.ny + c[1]
+                               : (oa == 1 ? (int64_t)c[2] * p.nx + c[0]
+                                          : (int64_t)c[1] * p.nx + c[0]);
+    return (T)ghost[oa][gi];
+  };
+  // plane value P(zl): the x/y interpolation of the four taps of plane zl
+  auto plane = [&](int zl) -> T {
+    const T a0 = tap(x, y, zl), a1 = tap(x - sx, y, zl);
+    const T b0 = tap(x, y - sy, zl), b1 = tap(x - sx, y - sy, zl);
+    return interp4(d, a0, a1, b0, b1);
+  };
+  const T dz = d.delta[2], dz1 = T(1) - d.delta[2];
+  // I*(z) = (1 - dz) P(z) + dz P(z - sz), marching up in z with one carried
+  // plane value: P(z - 1) when sz > 0, P(z) when sz < 0
+  T carry = sz > 0 ? plane(zb - 1) : (sz < 0 ? plane(zb) : T(0));
+  // detector: the cells on `face` for a direction that leaves through it
+  bool det = false;
+  T dw = T(0);
+  if (REV && face >= 0) {
+    const int a = face >> 1;
+    const bool hi = (face & 1) != 0;
+    const bool leaves = hi ? d.s[a] > 0 : d.s[a] < 0;
+    det = leaves && !p.periodic[a];
+    dw = d.delta[a];
   }
-  return acc;
+  for (int z = zb; z < ze; ++z) {
+    T v;
+    if (sz > 0) {
+      const T pz = plane(z);
+      v = fma(dz, carry, dz1 * pz);
+      carry = pz;
+    } else if (sz < 0) {
+      const T pn = plane(z + 1);
+      v = fma(dz, pn, dz1 * carry);
+      carry = pn;
+    } else {
+      v = plane(z);
+    }
+    if (REV && det) {
+      const int a = face >> 1;
+      const int ra = a == 0 ? x : (a == 1 ? y : z);
+      if (ra == ((face & 1) ? n3[a] - 1 : 0)) v += dw;
+    }
+    out[d.plane_el + (int64_t)z * pc + (int64_t)y * p.nx + x] = v;
+  }
 }
 
+// Per cell: nu = (dC/dI*)^T lambda' from I* (in nu on entry) and lambda',
+// and the coefficient gradients.  Pass 1 forms every sum at once: the part
+// of sum_i lambda'_i a_i D_i I'_i that depends on J is split off
+// (I'_i = a_i (I*_i + c_i (eta + ks J))), so J is not needed until after
+// the pass.  Pass 2 writes nu over I*.
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-adj_collide_kernel(const T *__restrict__ I, const T *__restrict__ lam, T *__restrict__ nu,
-                   T *__restrict__ g_ka, T *__restrict__ g_ks, T *__restrict__ g_eta,
-                   const float *__restrict__ ka, const float *__restrict__ ks,
-                   const float *__restrict__ eta, const float *__restrict__ vel,
-                   const DirTab<T> *__restrict__ tab, const KParams p,
-                   const InflowArgs *__restrict__ inflow) {
+adj_collide_kernel(const T *__restrict__ lam, T *__restrict__ nu, T *__restrict__ g_ka,
+                   T *__restrict__ g_ks, T *__restrict__ g_eta, const float *__restrict__ ka,
+                   const float *__restrict__ ks, const float *__restrict__ eta,
+                   const float *__restrict__ vel, const DirTab<T> *__restrict__ tab,
+                   const KParams p) {
   const int64_t cell = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (cell >= p.ncell) return;
-  const int x = (int)(cell % p.nx);
-  const int y = (int)((cell / p.nx) % p.ny);
-  const int z = (int)(cell / ((int64_t)p.nx * p.ny));
   const T dt = (T)p.dt;
   const T kat = (T)ka[cell], kst = (T)ks[cell], et = (T)eta[cell];
   T vx = T(0), vy = T(0), vz = T(0);
@@ -89,95 +149,67 @@ adj_collide_kernel(const T *__restrict__ I, const T *__restrict__ lam, T *__rest
     vy = (T)vel[p.ncell + cell];
     vz = (T)vel[2 * p.ncell + cell];
   }
-  const T W = T(1) / sqrt(T(1) - (vx * vx + vy * vy + vz * vz));
-  const T kt = kat + kst;
-  // pass 1: I*_i (kept in nu), and the sums of A, B, dA, dB
-  T sA = T(0), sB = T(0), sdA = T(0), sdB = T(0);
-  for (int k = 0; k < p.ndir; ++k) {
-    const DirTab<T> &d = tab[k];
-    const T Is = pull8<T>(I, d, inflow->ghost[k], x, y, z, p);
-    nu[d.plane_el + cell] = Is;
-    const T D = T(1) - (vx * d.n[0] + vy * d.n[1] + vz * d.n[2]);
-    const T a = T(1) / (T(1) + dt * W * D * kt);
-    sA = fma(D * D * a, Is, sA);
-    sB += d.w * a / D;
-    sdA = fma(D * D * D * a * a, Is, sdA);
-    sdB += d.w * a * a;
-  }
-  const T A = W * W * sA;
-  const T B = dt / W * sB;
-  const T den = T(1) - kst * B;
-  const T J = (A + et * B) / den;
+  const T W = div_fast(T(1), sqrt(T(1) - (vx * vx + vy * vy + vz * vz)));
   const T W3 = W * W * W;
-  // pass 2: G = sum lambda'_i a_i c_i, and sum lambda'_i a_i D_i I'_i
-  T G = T(0), sM = T(0);
+  const T dtWk = dt * W * (kat + kst);
+  T sA = T(0), sB = T(0), sdA = T(0), sdB = T(0), G = T(0), sM1 = T(0), sM2 = T(0);
   for (int k = 0; k < p.ndir; ++k) {
     const DirTab<T> &d = tab[k];
     const T Is = nu[d.plane_el + cell];
     const T mu = lam[d.plane_el + cell];
     const T D = T(1) - (vx * d.n[0] + vy * d.n[1] + vz * d.n[2]);
-    const T a = T(1) / (T(1) + dt * W * D * kt);
-    const T c = dt * d.w / (W3 * D * D * D);
-    const T Ip = a * (Is + c * (et + kst * J));
+    const T iD = div_fast(T(1), D);
+    const T a = div_fast(T(1), fma(dtWk, D, T(1)));
+    const T c = dt * d.w * iD * iD * iD / W3;
+    sA = fma(D * D * a, Is, sA);
+    sB = fma(d.w * a, iD, sB);
+    sdA = fma(D * D * D * a * a, Is, sdA);
+    sdB = fma(d.w * a, a, sdB);
     G = fma(mu, a * c, G);
-    sM = fma(mu * a * D, Ip, sM);
+    const T mad = mu * a * a * D;
+    sM1 = fma(mad, Is, sM1);
+    sM2 = fma(mad, c, sM2);
   }
+  const T A = W * W * sA;
+  const T B = dt / W * sB;
+  const T den = T(1) - kst * B;
+  const T J = div_fast(A + et * B, den);
+  const T sM = fma(et + kst * J, sM2, sM1);
   const T dA = -dt * W3 * sdA;
   const T dB = -dt * dt * sdB;
-  const T dJa = (dA + et * dB + J * kst * dB) / den;
-  const T dJs = (dA + et * dB + J * (kst * dB + B)) / den;
+  const T dJa = div_fast(dA + et * dB + J * kst * dB, den);
+  const T dJs = div_fast(dA + et * dB + J * (kst * dB + B), den);
   g_ka[cell] += -dt * W * sM + kst * G * dJa;
   g_ks[cell] += -dt * W * sM + G * (J + kst * dJs);
-  g_eta[cell] += G / den;
-  // pass 3: nu_i
-  const T h = kst * W * W * G / den;
+  g_eta[cell] += div_fast(G, den);
+  const T h = div_fast(kst * W * W * G, den);
   for (int k = 0; k < p.ndir; ++k) {
     const DirTab<T> &d = tab[k];
     const T mu = lam[d.plane_el + cell];
     const T D = T(1) - (vx * d.n[0] + vy * d.n[1] + vz * d.n[2]);
-    const T a = T(1) / (T(1) + dt * W * D * kt);
+    const T a = div_fast(T(1), fma(dtWk, D, T(1)));
     nu[d.plane_el + cell] = a * fma(h, D * D, mu);
   }
 }
 
-// lambda_i(r) = d_i(r) + sum_b w_b nu_i(r + b.s_i): the transpose of the pull
-// (sources outside the box are ghosts and get nothing; periodic axes wrap).
 template <typename T>
-__global__ void __launch_bounds__(kBlock)
-adj_transpose_kernel(const T *__restrict__ nu, T *__restrict__ lam,
-                     const DirTab<T> *__restrict__ tab, const KParams p, int face) {
-  const int64_t total = p.ncell * p.ndir;
-  const int n3[3] = {p.nx, p.ny, p.nz};
-  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * kBlock) {
-    const int k = (int)(e / p.ncell);
-    const int64_t cell = e - (int64_t)k * p.ncell;
-    const DirTab<T> &d = tab[k];
-    const int r[3] = {(int)(cell % p.nx), (int)((cell / p.nx) % p.ny),
-                      (int)(cell / ((int64_t)p.nx * p.ny))};
-    T acc = T(0);
-    for (int b = 0; b < 8; ++b) {
-      const T wt = d.tw[b];
-      if (wt == T(0)) continue;
-      int c[3] = {r[0] + (b & 1) * d.s[0], r[1] + ((b >> 1) & 1) * d.s[1],
-                  r[2] + (b >> 2) * d.s[2]};
-      bool in = true;
-      for (int a = 0; a < 3; ++a) {
-        if (p.periodic[a]) c[a] = wrap(c[a], n3[a]);
-        in = in && (unsigned)c[a] < (unsigned)n3[a];
-      }
-      if (in) acc = fma(wt, nu[d.plane_el + ((int64_t)c[2] * p.ny + c[1]) * p.nx + c[0]], acc);
-    }
-    if (face >= 0) {
-      // detector: the part of the population that leaves through the face
-      const int a = face >> 1;
-      const bool hi = (face & 1) != 0;
-      const bool on = hi ? r[a] == n3[a] - 1 : r[a] == 0;
-      const bool leaves = hi ? d.s[a] > 0 : d.s[a] < 0;
-      if (on && leaves && !p.periodic[a]) acc += d.delta[a];
-    }
-    lam[d.plane_el + cell] = acc;
-  }
+void launch_adjoint_t(const void *I, const void *lam_next, void *lam_out, void *nu, int face,
+                      void *g_ka, void *g_ks, void *g_eta, const float *ka, const float *ks,
+                      const float *eta, const float *vel, const void *tab, const KParams &p,
+                      const InflowArgs *inflow, hipStream_t s) {
+  const int nc = (int)((p.ncell + kBlock - 1) / kBlock);
+  const int ntx = (p.nx + 63) >> 6, nty = (p.ny + kPullRows - 1) / kPullRows;
+  const int nzr = (p.nz + kPullZlen - 1) / kPullZlen;
+  const dim3 pg((unsigned)(ntx * nty * nzr), (unsigned)p.ndir);
+  const DirTab<T> *t = static_cast<const DirTab<T> *>(tab);
+  hipLaunchKernelGGL((adj_pull_kernel<T, false>), pg, dim3(64 * kPullRows), 0, s,
+                     static_cast<const T *>(I), static_cast<T *>(nu), t, p, inflow, -1);
+  hipLaunchKernelGGL(adj_collide_kernel<T>, dim3(nc), dim3(kBlock), 0, s,
+                     static_cast<const T *>(lam_next), static_cast<T *>(nu),
+                     static_cast<T *>(g_ka), static_cast<T *>(g_ks), static_cast<T *>(g_eta),
+                     ka, ks, eta, vel, t, p);
+  hipLaunchKernelGGL((adj_pull_kernel<T, true>), pg, dim3(64 * kPullRows), 0, s,
+                     static_cast<const T *>(nu), static_cast<T *>(lam_out), t, p, inflow, face);
 }
 
 }  // namespace
@@ -187,30 +219,12 @@ hipError_t launch_adjoint(int storage, const void *I, const void *lam_next, void
                           const float *ka, const float *ks, const float *eta, const float *vel,
                           const void *tab, const KParams &p, const InflowArgs *inflow,
                           hipStream_t s) {
-  const int nb = (int)((p.ncell + kBlock - 1) / kBlock);
-  const int64_t tot = p.ncell * p.ndir;
-  const int nb2 = (int)std::min<int64_t>((tot + kBlock - 1) / kBlock, 65536);
-  if (storage == LBRT_FP64) {
-    using T = double;
-    hipLaunchKernelGGL(adj_collide_kernel<T>, dim3(nb), dim3(kBlock), 0, s,
-                       static_cast<const T *>(I), static_cast<const T *>(lam_next),
-                       static_cast<T *>(nu), static_cast<T *>(g_ka), static_cast<T *>(g_ks),
-                       static_cast<T *>(g_eta), ka, ks, eta, vel,
-                       static_cast<const DirTab<T> *>(tab), p, inflow);
-    hipLaunchKernelGGL(adj_transpose_kernel<T>, dim3(nb2), dim3(kBlock), 0, s,
-                       static_cast<const T *>(nu), static_cast<T *>(lam_out),
-                       static_cast<const DirTab<T> *>(tab), p, face);
-  } else {
-    using T = float;
-    hipLaunchKernelGGL(adj_collide_kernel<T>, dim3(nb), dim3(kBlock), 0, s,
-                       static_cast<const T *>(I), static_cast<const T *>(lam_next),
-                       static_cast<T *>(nu), static_cast<T *>(g_ka), static_cast<T *>(g_ks),
-                       static_cast<T *>(g_eta), ka, ks, eta, vel,
-                       static_cast<const DirTab<T> *>(tab), p, inflow);
-    hipLaunchKernelGGL(adj_transpose_kernel<T>, dim3(nb2), dim3(kBlock), 0, s,
-                       static_cast<const T *>(nu), static_cast<T *>(lam_out),
-                       static_cast<const DirTab<T> *>(tab), p, face);
-  }
+  if (storage == LBRT_FP64)
+    launch_adjoint_t<double>(I, lam_next, lam_out, nu, face, g_ka, g_ks, g_eta, ka, ks, eta,
+                             vel, tab, p, inflow, s);
+  else
+    launch_adjoint_t<float>(I, lam_next, lam_out, nu, face, g_ka, g_ks, g_eta, ka, ks, eta,
+                            vel, tab, p, inflow, s);
   return hipGetLastError();
 }
 
