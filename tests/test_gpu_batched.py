@@ -120,3 +120,36 @@ def test_batched_matches_oracle_on_sampled_domains():
                   "batched form runs one multi-domain launch per step instead")
 def test_persistent_single_launch_batched_kernel():
     pass
+
+
+def test_c4_recipe_domains_bitwise_and_oracle():
+    """16 domains drawn with the sweep's own recipe (edges 24..96, 50..400
+    steps, zero start): batched equals one-by-one bit for bit on all, and the
+    smallest domain matches the FP64 oracle over its full run."""
+    torch = gh.torch_mod()
+    L = gh.lib()
+    probs = [wl.batch_domain(d, seed=4) for d in range(16)]
+    for p in probs:
+        p.I0 = np.zeros((p.ndir,) + p.shape)
+    print([(p.nx, p.steps) for p in probs], flush=True)
+    doms = _setup(probs, L, torch)
+    b = L.lbrt_batch_create(doms)
+    L.lbrt_step_batched(b)
+    torch.cuda.synchronize()
+    for p, dm in zip(probs, doms):
+        Ia, Ib = dm["I0"].clone(), torch.zeros_like(dm["I0"])
+        E = torch.zeros(p.ncell, device="cuda")
+        L.lbrt_step(dm["ctx"], Ia, Ib, dm["kappa_a"], dm["kappa_s"], dm["eta"],
+                    nsteps=p.steps, E=E)
+        ref = Ib if p.steps % 2 == 1 else Ia
+        torch.cuda.synchronize()
+        assert torch.equal(_result(dm), ref), p.name
+        assert torch.equal(dm["E"], E), p.name
+    k = min(range(16), key=lambda j: (probs[j].ncell, probs[j].steps))
+    p = probs[k]
+    I = orc.run(p, I0=np.zeros((p.ndir,) + p.shape))
+    got = _result(doms[k]).double().cpu().numpy().reshape(I.shape)
+    err = gh.rel_l2(got, I)
+    print(p.name, p.shape, p.steps, f"{err:.2e}", flush=True)
+    assert err < 1e-5
+    b.close()
