@@ -33,6 +33,11 @@
  *     asynchronous; errors detected on the host are returned before any
  *     launch.  Every call returns an lbrt_status code and never aborts;
  *     lbrt_last_error() gives a message for the calling thread.
+ *   - A context owns work memory that its calls reuse (diagnostic partials,
+ *     the inflow ghost table, the adjoint's work state).  Calls on one
+ *     context must therefore be ordered: issue them on one stream, or
+ *     synchronise between streams.  Calls on different contexts are
+ *     independent.
  */
 #ifndef LBRT_H
 #define LBRT_H
