@@ -37,6 +37,11 @@ struct DirTab {
   int64_t plane_off;// byte offset of the direction's plane: plane * ncell * size
   T w;              // quadrature weight
   T n[3];           // unit direction
+  // Per-cell flux sums are formed against an isotropic reference (see the
+  // step kernel): 1 / w (0 for a null slot), and the sum of n_i w_i over the
+  // slots of the wave that owns this slot, in FP64 from the stored n and w.
+  T invw;
+  double nwq[3];
   T delta[3];       // dt |n^a| / dx, the fraction pulled from the upwind cell
   T scale;          // storage scale s_i (1 for FP32/FP64)
   T inv_scale;      // 1 / s_i
@@ -55,6 +60,10 @@ struct InflowArgs {
   // along a (the low face when s_a > 0, the high face when s_a < 0), or null.
   const float *ghost[LBRT_MAX_DIRS][3];
 };
+
+// Waves per block of the step kernels (the wave q owns direction slots
+// [q NB / waves, (q + 1) NB / waves)).
+constexpr int waves_for(int nb) { return nb >= 112 ? 8 : 4; }
 
 enum : uint32_t {
   KF_PAIRED = 1u << 0,   // directions come in antipodal pairs (2k, 2k+1)

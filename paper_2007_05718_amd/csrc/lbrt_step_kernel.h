@@ -184,7 +184,6 @@ __device__ inline void block_sums(const double (&v)[M], double *out) {
 // Waves per block of the step kernels for a bucket of NB direction slots:
 // about 14 slots per wave keeps a lane's streamed and carried values in
 // registers without spilling.
-constexpr int waves_for(int nb) { return nb >= 112 ? 8 : 4; }
 // Waves per SIMD the main kernel is compiled for: the second argument of
 // __launch_bounds__ is the minimum number of waves per execution unit (SIMD),
 // which caps VGPRs at 512 / that.  Two 8-wave blocks per CU (4 waves per SIMD,
@@ -198,14 +197,17 @@ constexpr int waves_per_simd(int nb) { return sizeof(S) == 2 ? (nb >= 112 ? 2 : 
 // Main path: slots whose four taps are in flight ahead of the slot being
 // interpolated, for M slots per wave (memory-level parallelism per wave;
 // each costs 4 VGPRs: 4 ahead fit the 128-VGPR budget at M = 14, 3 at 19).
-// FP64 taps take two VGPRs each, so FP64 keeps 2 slots ahead.
+// FP64 taps take two VGPRs each, so FP64 keeps 2 slots ahead; the 16-bit
+// forms (which need a few more VGPRs for their conversions) and the moving
+// fluid keep 3, which holds them under 128 VGPRs without spills.
 #ifdef LBRT_PF_DEPTH
-template <typename S>
+template <typename S, bool MOVING = false>
 constexpr int pf_depth(int m) { return m < LBRT_PF_DEPTH ? m : LBRT_PF_DEPTH; }
 #else
-template <typename S>
+template <typename S, bool MOVING = false>
 constexpr int pf_depth(int m) {
-  return sizeof(S) == 8 ? (m < 2 ? m : 2) : (m <= 14 ? (m < 4 ? m : 4) : 3);
+  const int d = sizeof(S) == 8 ? 2 : ((sizeof(S) == 2 || MOVING || m > 14) ? 3 : 4);
+  return m < d ? m : d;
 }
 #endif
 
@@ -363,27 +365,37 @@ __device__ inline T ghost_influx(const DirTab<T> &d, const float *g, int a, int 
 //     otherwise;
 //   moving fluid: E*, A = sum D_i^2 a_i I*_i and B = sum w_i a_i / D_i (App. B).
 // ---------------------------------------------------------------------------
+// Per-lane moment sums of a wave's slots.  In an optically thick cell I_i is
+// close to w_i E, so F = sum n_i I_i is a small difference of terms of size
+// E, and plain FP32 partial sums would lose about eps_32 E of it.  The flux
+// is therefore summed as residuals against an isotropic reference ref (the
+// wave's first slot, I_0 / w_0):
+//   sum_i n_i I_i = sum_i n_i (I_i - w_i ref) + ref sum_i n_i w_i,
+// the residuals are O(F) in a thick cell, and the last term (the wave's
+// sum of n_i w_i is a table constant) is added in FP64 when the waves'
+// partial sums are combined.
 template <typename T>
 struct Acc {
   T Es = T(0), F0 = T(0), F1 = T(0), F2 = T(0);  // static (F0..F2) or moving (F0 = A, F1 = B)
+  T ref = T(0);
 };
 
 template <bool MOVING, int J, int M, typename T>
 __device__ __forceinline__ void accumulate(Acc<T> &m, const DirTab<T> *__restrict__ tb,
                                            const T *Is, T vx, T vy, T vz, T dtWk) {
+  const DirTab<T> &d = tb[J];
+  m.Es += Is[J];
   if constexpr (MOVING) {
-    const DirTab<T> &d = tb[J];
-    m.Es += Is[J];
     const T D = T(1) - (vx * d.n[0] + vy * d.n[1] + vz * d.n[2]);
     const T a = rcp<T>(fma(dtWk, D, T(1)));
     m.F0 = fma(D * D * a, Is[J], m.F0);
     m.F1 = fma(d.w * a, rcp<T>(D), m.F1);
   } else {
-    const DirTab<T> &d = tb[J];
-    m.Es += Is[J];
-    m.F0 = fma(d.n[0], Is[J], m.F0);
-    m.F1 = fma(d.n[1], Is[J], m.F1);
-    m.F2 = fma(d.n[2], Is[J], m.F2);
+    if constexpr (J == 0) m.ref = Is[0] * d.invw;
+    const T r = fma(-d.w, m.ref, Is[J]);
+    m.F0 = fma(d.n[0], r, m.F0);
+    m.F1 = fma(d.n[1], r, m.F1);
+    m.F2 = fma(d.n[2], r, m.F2);
   }
 }
 
@@ -526,7 +538,9 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
     unroll<0, M>(pro);
   }
 
-  __shared__ T red[2][NW][4][64];
+  // the waves' partial sums per plane (double-buffered): E, three flux sums
+  // and the wave's isotropic reference
+  __shared__ T red[2][NW][5][64];
   // element offsets of the new planes of output plane z: z (sz >= 0) and the
   // plane above (sz < 0), clamped into the box on a non-periodic axis
   auto plane_above = [&](int z) {
@@ -536,7 +550,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
   // Main path: the taps of slots [J, J + D) of the plane are in flight
   // while slot J is interpolated; the first D of the next plane go out
   // before the collision's stores.
-  constexpr int D = pf_depth<S>(M);
+  constexpr int D = pf_depth<S, MOVING>(M);
   T pf[M][4];
   auto issue_first = [&](int zn) {
     const int64_t czn = (int64_t)zn * pc, czn1 = plane_above(zn);
@@ -663,6 +677,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
     red[par][q][1][lane] = m.F0;
     red[par][q][2][lane] = m.F1;
     red[par][q][3][lane] = m.F2;
+    red[par][q][4][lane] = m.ref;
     __syncthreads();
     auto comb = [&](int b, int j) {
       T v[NW];
@@ -670,7 +685,27 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
       for (int w = 0; w < NW; ++w) v[w] = red[b][w][j][lane];
       return tree_sum<T, NW>(v);
     };
-    const T Es = comb(par, 0), S0 = comb(par, 1), S1 = comb(par, 2), S2 = comb(par, 3);
+    // flux a of a combine: the residual sums plus, in FP64 and in wave
+    // order, sum over waves of ref_w (sum of n_i w_i over wave w's slots)
+    const DirTab<T> *__restrict__ tz = tab + (z & 1) * NB;
+    auto flux = [&](int b, int a) -> T {
+      double s = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) s = fma((double)red[b][w][4][lane], tz[w * M].nwq[a], s);
+      return (T)((double)comb(b, 1 + a) + s);
+    };
+    const T Es = comb(par, 0);
+    const T EsT = Es;
+    T S0, S1, S2;
+    if constexpr (MOVING) {
+      S0 = comb(par, 1);
+      S1 = comb(par, 2);
+      S2 = T(0);
+    } else {
+      S0 = flux(par, 0);
+      S1 = flux(par, 1);
+      S2 = flux(par, 2);
+    }
 
 
     // the next plane's first loads go out before the collision's stores
@@ -692,32 +727,32 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
       if (p.mode == LBRT_COLL_EXPLICIT) {
         // eq. (collision-step) with I^eq and S of eq. (source-and-equil)
         c = T(1) - dt * (kst + kat);
-        alpha = dt * (kst * Es + et);
+        alpha = dt * (kst * EsT + et);
         const T g = dt * kst * lam;
         be0 = g * F0; be1 = g * F1; be2 = g * F2;
-        En = c * Es + alpha;
+        En = c * EsT + alpha;
         Fn0 = fma(be0, third, c * F0); Fn1 = fma(be1, third, c * F1); Fn2 = fma(be2, third, c * F2);
       } else if (p.mode == LBRT_COLL_LAMBDA) {
         // Lambda iteration: (E, F) <- moments of the decoupled solution,
         // which the rule's identities reduce to a scalar recursion per cell.
         c = div_fast(T(1), T(1) + dt * (kst + kat));
-        T Ek = Es, G0 = F0, G1 = F1, G2 = F2;
+        T Ek = EsT, G0 = F0, G1 = F1, G2 = F2;
         const T h = dt * kst * lam * third;
         for (int it = 1; it < p.lambda_iters; ++it) {
-          Ek = c * (Es + dt * (kst * Ek + et));
+          Ek = c * (EsT + dt * (kst * Ek + et));
           G0 = c * (F0 + h * G0); G1 = c * (F1 + h * G1); G2 = c * (F2 + h * G2);
         }
         alpha = c * dt * (kst * Ek + et);
         const T g = c * dt * kst * lam;
         be0 = g * G0; be1 = g * G1; be2 = g * G2;
-        En = c * Es + alpha;
+        En = c * EsT + alpha;
         Fn0 = fma(be0, third, c * F0); Fn1 = fma(be1, third, c * F1); Fn2 = fma(be2, third, c * F2);
       } else {
         // eq. (rte_implicit) solved exactly: the moment equations decouple to
         // E = (E* + dt eta)/(1 + dt ka), F = F*/(1 + dt(k0 + ka) - dt k0 lam/3).
         const T den = T(1) + dt * (kst + kat);
         c = div_fast(T(1), den);
-        En = div_fast(Es + dt * et, T(1) + dt * kat);
+        En = div_fast(EsT + dt * et, T(1) + dt * kat);
         const T gF = div_fast(T(1), den - dt * kst * lam * third);
         Fn0 = F0 * gF; Fn1 = F1 * gF; Fn2 = F2 * gF;
         alpha = c * dt * (kst * En + et);
@@ -756,11 +791,13 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
       //   J = (A + eta B) / (1 - k0 B),  A = W^2 sum D_i^2 a_i I*_i,
       //   B = (dt/W) sum w_i a_i / D_i,
       //   I_i = a_i [I*_i + dt w_i (eta + k0 J) / (W^3 D_i^3)].
-      const T A = S0 * (W * W);
-      const T B = S1 * (dt / W);
-      const T J = div_fast(A + et * B, T(1) - kst * B);
+      // J in FP64: with kappa_a << kappa_s the denominator 1 - k0 B is a
+      // small difference
+      const double A = (double)S0 * (double)(W * W);
+      const double B = (double)S1 * (double)(dt / W);
+      const T J = (T)((A + (double)et * B) / (1.0 - (double)kst * B));
       const T gam = div_fast(dt * (et + kst * J), W * W * W);
-      T e = T(0), f0 = T(0), f1 = T(0), f2 = T(0);
+      T e = T(0), f0 = T(0), f1 = T(0), f2 = T(0), ref = T(0);
       if (valid) {
 #pragma unroll
         for (int j = 0; j < M; ++j) {
@@ -770,10 +807,13 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
             const T a = rcp<T>(fma(dtWk, D, T(1)));
             const T iD = rcp<T>(D);
             const T o = a * fma(d.w * gam, iD * iD * iD, Is[j]);
+            // (flux as residuals against the wave's first slot, as above)
+            if (j == 0) ref = o * d.invw;
+            const T r = fma(-d.w, ref, o);
             e += o;
-            f0 = fma(d.n[0], o, f0);
-            f1 = fma(d.n[1], o, f1);
-            f2 = fma(d.n[2], o, f2);
+            f0 = fma(d.n[0], r, f0);
+            f1 = fma(d.n[1], r, f1);
+            f2 = fma(d.n[2], r, f2);
             Tr::st(reinterpret_cast<S *>(reinterpret_cast<char *>(outz + d.plane_off / SZ) +
                                          o0),
                    Tr::kReduced ? o * d.inv_scale : o);
@@ -787,11 +827,12 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
       red[par ^ 1][q][1][lane] = f0;
       red[par ^ 1][q][2][lane] = f1;
       red[par ^ 1][q][3][lane] = f2;
+      red[par ^ 1][q][4][lane] = ref;
       __syncthreads();
       En = comb(par ^ 1, 0);
-      Fn0 = comb(par ^ 1, 1);
-      Fn1 = comb(par ^ 1, 2);
-      Fn2 = comb(par ^ 1, 3);
+      Fn0 = flux(par ^ 1, 0);
+      Fn1 = flux(par ^ 1, 1);
+      Fn2 = flux(par ^ 1, 2);
       // The next plane writes red[par ^ 1] only after every wave has read it.
       __syncthreads();
     }
