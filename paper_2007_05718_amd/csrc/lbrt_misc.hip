@@ -15,21 +15,24 @@ moments_kernel(const S *__restrict__ I, const DirTab<typename StoreTraits<S>::T>
   using T = typename Tr::T;
   const int64_t cell = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (cell >= ncell) return;
-  T e = T(0), f0 = T(0), f1 = T(0), f2 = T(0);
+  // FP64 sums (one thread per cell, memory-bound): in an optically thick
+  // cell F is a small difference of terms of size E
+  double e = 0.0, f0 = 0.0, f1 = 0.0, f2 = 0.0;
   for (int i = 0; i < ndir; ++i) {
     const DirTab<T> &d = tab[i];
     T v = Tr::ld(I + (int64_t)d.plane * ncell + cell);
     if (Tr::kReduced) v *= d.scale;
-    e += v;
-    f0 = fma(d.n[0], v, f0);
-    f1 = fma(d.n[1], v, f1);
-    f2 = fma(d.n[2], v, f2);
+    const double vd = (double)v;
+    e += vd;
+    f0 = fma((double)d.n[0], vd, f0);
+    f1 = fma((double)d.n[1], vd, f1);
+    f2 = fma((double)d.n[2], vd, f2);
   }
-  if (E) E[cell] = e;
+  if (E) E[cell] = (T)e;
   if (F) {
-    F[cell] = f0;
-    F[ncell + cell] = f1;
-    F[2 * ncell + cell] = f2;
+    F[cell] = (T)f0;
+    F[ncell + cell] = (T)f1;
+    F[2 * ncell + cell] = (T)f2;
   }
 }
 
