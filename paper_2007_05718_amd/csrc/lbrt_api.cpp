@@ -126,7 +126,7 @@ int default_zlen(int nx, int ny, int nz, const TileShape &t) {
 template <typename T>
 void build_table(const lbrt_ctx &c, std::vector<DirTab<T>> &tab) {
   const lbrt_desc &d = c.desc;
-  tab.assign(2 * (size_t)c.nb, DirTab<T>{});
+  tab.assign((size_t)c.nb, DirTab<T>{});
   const double dx = d.dx, dt = d.dt;
   const int64_t ncell = (int64_t)d.nx * d.ny * d.nz;
   const int64_t esize = (int64_t)storage_bytes(d.storage);
@@ -179,8 +179,10 @@ void build_table(const lbrt_ctx &c, std::vector<DirTab<T>> &tab) {
     e.mxp = s[0] > 0 ? 0xffffffffu : 0u;
     e.mxm = s[0] < 0 ? 0xffffffffu : 0u;
     e.dzn = s[2] < 0 ? 1 : 0;
+    e.dzn_a = e.dzn;
     e.active = 1;
     e.row_shift = -s[1] * d.nx;
+    e.row_off = (int64_t)e.row_shift * esize;
     e.w = (T)c.weights[i];
     for (int a = 0; a < 3; ++a) {
       e.n[a] = (T)n[a];
@@ -203,7 +205,6 @@ void build_table(const lbrt_ctx &c, std::vector<DirTab<T>> &tab) {
     for (int k = q * m; k < (q + 1) * m; ++k)
       for (int a = 0; a < 3; ++a) tab[k].nwq[a] = nw[a];
   }
-  for (int k = 0; k < c.nb; ++k) tab[c.nb + k] = tab[k];
 }
 
 int ensure_partials(lbrt_ctx *c, int nblocks) {

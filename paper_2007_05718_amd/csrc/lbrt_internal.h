@@ -17,34 +17,42 @@ struct f16_t { uint16_t u; };
 // so every tap of an in-box cell is an in-box address.
 template <typename T>
 struct DirTab {
-  T tw[8];          // trilinear tap weights, tap b = bx | by << 1 | bz << 2 (eq. interp)
-  // The same weights per axis: wx = (1 - delta_x, delta_x), likewise wy; the
-  // z pair is stored as (weight of the newly loaded plane, weight of the
-  // carried plane) in the z-march order: (1 - delta_z, delta_z) when
-  // s_z >= 0, (delta_z, 1 - delta_z) when s_z < 0.
+  // The z-march reads two groups of fields per slot and plane, each laid out
+  // contiguously so that it arrives in one or two wide scalar loads: the
+  // interpolation and moment constants of the slot being streamed, and the
+  // addresses of the slot whose loads are issued ahead.
+  //
+  // Weights per axis: wx = (1 - delta_x, delta_x), likewise wy; the z pair is
+  // stored as (weight of the newly loaded plane, weight of the carried plane)
+  // in the z-march order: (1 - delta_z, delta_z) when s_z >= 0,
+  // (delta_z, 1 - delta_z) when s_z < 0.
   T wx[2], wy[2];
   T wz_new, wz_old;
-  T dxs;            // delta_x * scale: x-face outflux per stored unit
-  // Main-path constants of the z-march: sx > 0 / sx < 0 as 0/1 factors and
-  // as all-ones/zero masks, the new plane's z offset (1 when sz < 0), and the
-  // element shift of the y-halo row (-sy * nx).
-  T cxp, cxm;
-  uint32_t mxp, mxm;
-  int32_t dzn;
-  int32_t row_shift;
+  int32_t dzn;      // the new plane's z offset: 1 when s_z < 0, else 0
   int32_t active;   // 1 for a direction, 0 for a null (padding) slot
-  int64_t plane_el; // element offset of the direction's plane: plane * ncell
-  int64_t plane_off;// byte offset of the direction's plane: plane * ncell * size
   T w;              // quadrature weight
   T n[3];           // unit direction
+  T scale;          // storage scale s_i (1 for FP32/FP64)
+  T inv_scale;      // 1 / s_i
   // Per-cell flux sums are formed against an isotropic reference (see the
   // step kernel): 1 / w (0 for a null slot), and the sum of n_i w_i over the
   // slots of the wave that owns this slot, in FP64 from the stored n and w.
   T invw;
+  T dxs;            // delta_x * scale: x-face outflux per stored unit
+  // Addresses: byte offsets of the direction's plane and of its y-halo row
+  // (-sy * nx cells), the sx > 0 / sx < 0 all-ones/zero masks that pick the
+  // lane's x-shifted offset, and dzn again (so that the group is one load).
+  int64_t plane_off;// plane * ncell * size
+  int64_t row_off;  // row_shift * size
+  uint32_t mxp, mxm;
+  int32_t dzn_a;
+  int32_t row_shift;// -sy * nx
+  // sx > 0 / sx < 0 as 0/1 factors (x-face tiles)
+  T cxp, cxm;
+  int64_t plane_el; // element offset of the direction's plane: plane * ncell
   double nwq[3];
+  T tw[8];          // trilinear tap weights, tap b = bx | by << 1 | bz << 2 (eq. interp)
   T delta[3];       // dt |n^a| / dx, the fraction pulled from the upwind cell
-  T scale;          // storage scale s_i (1 for FP32/FP64)
-  T inv_scale;      // 1 / s_i
   int32_t s[3];     // shift signs sgn(n^a), 0 where n^a == 0
   int32_t plane;    // storage plane (direction index in the caller's order)
 };

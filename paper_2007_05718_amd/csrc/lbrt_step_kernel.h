@@ -122,6 +122,15 @@ template <> __device__ __forceinline__ double zero_if<double>(double v, int zero
   return __longlong_as_double(__double_as_longlong(v) & ((long long)zero - 1));
 }
 
+// The same (wave-uniform) integer, which the compiler must treat as a new
+// value: loads at an offset made from it cannot be hoisted out of a loop or
+// merged with loads at another copy of it.  (An integer, not a pointer: the
+// pointer keeps its global address space and the loads stay scalar.)
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
+
 // Unrolled loop helper: calls f.template operator()<J>() for J = 0..N-1.
 template <int J, int N, typename F>
 __device__ __forceinline__ void unroll(F &f) {
@@ -453,10 +462,10 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
   const bool xface_tile = !perx && (x0 == 0 || x0 + p.tx >= nx);
   const bool face_tile = xface_tile || (!pery && (y0 == 0 || y0 + p.ty >= ny));
 
-  // This wave's slots.  The table holds two identical copies of the NB slots;
-  // plane z reads copy z & 1.  The table is thus re-read (scalar cache hits)
-  // on every plane instead of being hoisted out of the z loop, which would
-  // keep hundreds of uniform values live in SGPRs and spill them.
+  // This wave's slots.  Every plane re-reads them (scalar cache hits)
+  // through an opaque copy of the pointer: hoisted out of the z loop, they
+  // would keep hundreds of uniform values live in SGPRs and spill them.  One
+  // copy of the table keeps its footprint within the scalar cache.
   const DirTab<T> *__restrict__ tb = tab + q * M;
   const T dt = (T)p.dt;
 
@@ -483,14 +492,17 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
     }
     return P;
   };
-  // Main-path loads of the four taps of slot d from the plane whose element
-  // offset (z * pc) is cz: rows y and y - sy, each unshifted and x-shifted.
-  // The x-shifted offset is o0 plus the lane's delta for the slot's sign of
-  // sx, selected with the slot's all-ones/zero masks.
+  // Main-path loads of the four taps of slot d from the z-plane that starts
+  // at byte `plane` of the first direction's storage: rows y and y - sy, each
+  // unshifted and x-shifted.  The x-shifted offset is o0 plus the lane's
+  // delta for the slot's sign of sx, selected with the slot's all-ones/zero
+  // masks.  The row addresses are two 64-bit scalar adds per slot.
   const uint32_t dxp = oxp - o0, dxm = oxm - o0;
-  auto load4 = [&](const DirTab<T> &d, int64_t cz, T (&v)[4]) {
-    const S *r0 = Iin + d.plane_el + cz;
-    const S *r1 = r0 + d.row_shift;
+  const char *const in_bytes = reinterpret_cast<const char *>(Iin);
+  auto load4 = [&](const DirTab<T> &d, const char *plane, T (&v)[4]) {
+    const char *b0 = plane + d.plane_off;
+    const S *r0 = reinterpret_cast<const S *>(b0);
+    const S *r1 = reinterpret_cast<const S *>(b0 + d.row_off);
     const uint32_t a0 = o0;
     const uint32_t ax = a0 + (dxp & d.mxp) + (dxm & d.mxm);
     v[0] = ldo<S>(r0, a0);
@@ -526,7 +538,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
         if constexpr (MAIN) {
           T v[4];
           const bool in = (unsigned)zl < (unsigned)nz;
-          load4(d, (int64_t)min(max(zl, 0), nz - 1) * pc, v);
+          load4(d, in_bytes + (int64_t)min(max(zl, 0), nz - 1) * pc * SZ, v);
           const T k1 = xkeep(d);
           carry[J] = (in ? T(1) : T(0)) * interp4(d, v[0], v[1] * k1, v[2], v[3] * k1);
           if (diag && d.s[2] < 0) fx = fma(fma(d.cxp, xop, d.cxm * xom) * d.dxs, v[0], fx);
@@ -553,8 +565,9 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
   constexpr int D = pf_depth<S, MOVING>(M);
   T pf[M][4];
   auto issue_first = [&](int zn) {
-    const int64_t czn = (int64_t)zn * pc, czn1 = plane_above(zn);
-    auto one = [&]<int J>() { load4(tb[J], tb[J].dzn ? czn1 : czn, pf[J]); };
+    const char *const p0 = in_bytes + (int64_t)zn * pc * SZ;
+    const char *const p1 = in_bytes + plane_above(zn) * SZ;
+    auto one = [&]<int J>() { load4(tb[J], tb[J].dzn_a ? p1 : p0, pf[J]); };
     unroll<0, D>(one);
   };
   if constexpr (MAIN)
@@ -562,7 +575,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
 
   for (int z = zb; z < ze; ++z) {
     const int par = (z - zb) & 1;
-    tb = tab + (z & 1) * NB + q * M;
+    tb = tab + opaque(q * M);
     const int64_t cz = (int64_t)z * pc;
     const int64_t cell = cz + (int64_t)(o0 / (uint32_t)SZ);
 
@@ -587,29 +600,35 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
     T Is[M];
     Acc<T> m;
     if constexpr (MAIN) {
-      // A new plane above the box (sz < 0 on the last plane of a
-      // non-periodic z axis) is vacuum: its clamped loads get weight 0.
-      const int64_t cz1 = plane_above(z);
+      // the new planes: this one (sz >= 0) and the one above (sz < 0); a
+      // plane above a non-periodic box is clamped into it and weighted 0
+      const char *const p0 = in_bytes + cz * SZ;
+      const char *const p1 = in_bytes + plane_above(z) * SZ;
       // the plane above a non-periodic box is vacuum: weight 0
       const int gh = (!perz && z + 1 >= nz) ? 1 : 0;
       // the plane above the last plane of the range belongs to the next block
       const int lastz = z + 1 >= ze ? 1 : 0;
-      // BOOK: also book the x-face outflux of the own values (x-face tiles
-      // with diagnostics on; a block-uniform choice between two copies of
-      // the slot loop keeps the common one free of branches).  Slot J issues
-      // the loads of slot J + D before interpolating its own.
-      auto slot = [&]<int J, bool BOOK>() {
+      // FACE: a tile on a non-periodic x face.  Its face lanes zero the
+      // x-shifted taps that are ghosts, and the x-face outflux of the own
+      // values is booked (used with diagnostics on).  Every other tile takes
+      // the copy without either (for its lanes the factor is exactly 1, so
+      // both copies give the same bits).  Slot J issues the loads of slot
+      // J + D before interpolating its own.
+      auto slot = [&]<int J, bool FACE>() {
         const DirTab<T> &d = tb[J];
-        if constexpr (J + D < M) load4(tb[J + D], tb[J + D].dzn ? cz1 : cz, pf[J + D]);
+        if constexpr (J + D < M) load4(tb[J + D], tb[J + D].dzn_a ? p1 : p0, pf[J + D]);
         const T(&cur)[4] = pf[J];
-        const T k1 = xkeep(d);
-        const T Pn = interp4(d, cur[0], cur[1] * k1, cur[2], cur[3] * k1);
-        if constexpr (BOOK) {
+        T c1 = cur[1], c3 = cur[3];
+        if constexpr (FACE) {
+          const T k1 = xkeep(d);
+          c1 *= k1;
+          c3 *= k1;
           // the plane above the range belongs to the next block
           const T ko = fma(d.cxp, xop, d.cxm * xom);
           const T dxs = zero_if(d.dxs, d.dzn & lastz);
           fx = fma(ko * dxs, cur[0], fx);
         }
+        const T Pn = interp4(d, cur[0], c1, cur[2], c3);
         // the new plane above a non-periodic box is vacuum
         const T wn = zero_if(d.wz_new, d.dzn & gh);
         T sv = fma(d.wz_old, carry[J], wn * Pn);
@@ -618,10 +637,10 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
         carry[J] = Pn;
         accumulate<MOVING, J, M>(m, tb, Is, vx, vy, vz, dtWk);
       };
-      auto body_book = [&]<int J>() { slot.template operator()<J, true>(); };
+      auto body_face = [&]<int J>() { slot.template operator()<J, true>(); };
       auto body = [&]<int J>() { slot.template operator()<J, false>(); };
-      if (diag && xface_tile)
-        unroll<0, M>(body_book);
+      if (xface_tile)
+        unroll<0, M>(body_face);
       else
         unroll<0, M>(body);
     } else {
@@ -687,7 +706,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
     };
     // flux a of a combine: the residual sums plus, in FP64 and in wave
     // order, sum over waves of ref_w (sum of n_i w_i over wave w's slots)
-    const DirTab<T> *__restrict__ tz = tab + (z & 1) * NB;
+    const DirTab<T> *__restrict__ tz = tab + opaque(0);
     auto flux = [&](int b, int a) -> T {
       double s = 0.0;
 #pragma unroll
@@ -713,10 +732,10 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
       if (z + 1 < ze) issue_first(z + 1);
 
     S *const outz = Iout + cz;
-    // The collision reads the other copy of the table, so that its loads are
-    // not merged with the streaming phase's (which would keep those values
-    // live across the barrier).
-    const DirTab<T> *__restrict__ tbc = tab + ((z & 1) ^ 1) * NB + q * M;
+    // The collision reads the table through another opaque pointer, so that
+    // its loads are not merged with the streaming phase's (which would keep
+    // those values live across the barrier).
+    const DirTab<T> *__restrict__ tbc = tab + opaque(q * M);
     T En = T(0), Fn0 = T(0), Fn1 = T(0), Fn2 = T(0);
     if constexpr (!MOVING) {
       const T F0 = S0, F1 = S1, F2 = S2;
