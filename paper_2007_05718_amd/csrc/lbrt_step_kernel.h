@@ -573,24 +573,37 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
   if constexpr (MAIN)
     if (zb < ze) issue_first(zb);
 
+  // The medium of a plane (kappa_a, kappa_s, eta and, for a moving fluid,
+  // the velocity) is loaded during the previous plane, so that its use
+  // never waits for it.  Every lane's cell index is inside the box (invalid lanes
+  // read a clamped cell whose values are never stored or summed), so the
+  // loads need no guard: a guarded load into a zeroed register would make
+  // the compiler drain all outstanding memory operations at the zeroing.
+  T med[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+  auto load_medium = [&](int64_t c) {
+    med[0] = (T)ka[c];
+    med[1] = (T)ks[c];
+    med[2] = (T)eta[c];
+    if constexpr (MOVING) {
+      med[3] = (T)vel[c];
+      med[4] = (T)vel[p.ncell + c];
+      med[5] = (T)vel[2 * p.ncell + c];
+    }
+  };
+  load_medium((int64_t)zb * pc + (int64_t)(o0 / (uint32_t)SZ));
+
   for (int z = zb; z < ze; ++z) {
     const int par = (z - zb) & 1;
     tb = tab + opaque(q * M);
     const int64_t cz = (int64_t)z * pc;
     const int64_t cell = cz + (int64_t)(o0 / (uint32_t)SZ);
 
-    T kat = T(0), kst = T(0), et = T(0);
-    T vx = T(0), vy = T(0), vz = T(0);
-    if (valid) {
-      kat = (T)ka[cell];
-      kst = (T)ks[cell];
-      et = (T)eta[cell];
-      if constexpr (MOVING) {
-        vx = (T)vel[cell];
-        vy = (T)vel[p.ncell + cell];
-        vz = (T)vel[2 * p.ncell + cell];
-      }
-    }
+    // this plane's medium, loaded during the previous plane; the next
+    // plane's goes out once the collision has used this one (the last plane
+    // reloads its own cells)
+    const T kat = med[0], kst = med[1], et = med[2];
+    const T vx = med[3], vy = med[4], vz = med[5];
+    const int64_t cell_next = z + 1 < ze ? cell + pc : cell;
     T W = T(1), dtWk = T(0);
     if constexpr (MOVING) {
       W = T(1) / sqrt(T(1) - (vx * vx + vy * vy + vz * vz));
@@ -727,9 +740,13 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
     }
 
 
-    // the next plane's first loads go out before the collision's stores
-    if constexpr (MAIN)
-      if (z + 1 < ze) issue_first(z + 1);
+    // The next plane's first loads go out before the collision's stores,
+    // after the collision has read this plane's medium (loads complete in
+    // issue order, so a read of the medium behind them would wait for them).
+    auto issue_next = [&]() {
+      if constexpr (MAIN)
+        if (z + 1 < ze) issue_first(z + 1);
+    };
 
     S *const outz = Iout + cz;
     // The collision reads the table through another opaque pointer, so that
@@ -778,6 +795,8 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
         const T g = c * dt * kst * lam;
         be0 = g * Fn0; be1 = g * Fn1; be2 = g * Fn2;
       }
+      load_medium(cell_next);
+      issue_next();
       if (valid) {
         if (p.flags & KF_LAMZERO) {
 #pragma unroll
@@ -816,6 +835,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
       const double B = (double)S1 * (double)(dt / W);
       const T J = (T)((A + (double)et * B) / (1.0 - (double)kst * B));
       const T gam = div_fast(dt * (et + kst * J), W * W * W);
+      issue_next();
       T e = T(0), f0 = T(0), f1 = T(0), f2 = T(0), ref = T(0);
       if (valid) {
 #pragma unroll
@@ -839,6 +859,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
           }
         }
       }
+      load_medium(cell_next);
       // Moments of the new state, combined like the streamed ones through the
       // other half of the double buffer.  It is free: its last readers were
       // the previous plane's, and every wave has passed this plane's barrier.
