@@ -131,6 +131,20 @@ __device__ __forceinline__ int opaque(int v) {
   return v;
 }
 
+// A lane's value, which the compiler must treat as new: an address made from
+// it cannot be hoisted out of a loop (where it would hold a 64-bit VGPR pair
+// for the whole loop).
+__device__ __forceinline__ uint32_t opaque_lane(uint32_t v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+// Store at a wave-uniform base plus a lane's byte offset.
+template <typename S>
+__device__ __forceinline__ void sto(char *base, uint32_t byte_off, typename StoreTraits<S>::T v) {
+  StoreTraits<S>::st(reinterpret_cast<S *>(base + byte_off), v);
+}
+
 // Unrolled loop helper: calls f.template operator()<J>() for J = 0..N-1.
 template <int J, int N, typename F>
 __device__ __forceinline__ void unroll(F &f) {
@@ -748,7 +762,11 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
         if (z + 1 < ze) issue_first(z + 1);
     };
 
-    S *const outz = Iout + cz;
+    // the new populations of plane z: a uniform base per slot plus the
+    // lane's byte offset (made opaque so the per-lane 64-bit sum is not
+    // hoisted out of the z loop)
+    char *const outz = reinterpret_cast<char *>(Iout) + cz * SZ;
+    const uint32_t ost = opaque_lane(o0);
     // The collision reads the table through another opaque pointer, so that
     // its loads are not merged with the streaming phase's (which would keep
     // those values live across the barrier).
@@ -805,8 +823,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
             if (d.active) {
               T o = fma(c, Is[j], d.w * alpha);
               if (Tr::kReduced) o *= d.inv_scale;
-              Tr::st(reinterpret_cast<S *>(reinterpret_cast<char *>(outz + d.plane_off / SZ) +
-                                           o0), o);
+              sto<S>(outz + d.plane_off, ost, o);
             }
           }
         } else {
@@ -817,8 +834,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
               const T nb = alpha + d.n[0] * be0 + d.n[1] * be1 + d.n[2] * be2;
               T o = fma(c, Is[j], d.w * nb);
               if (Tr::kReduced) o *= d.inv_scale;
-              Tr::st(reinterpret_cast<S *>(reinterpret_cast<char *>(outz + d.plane_off / SZ) +
-                                           o0), o);
+              sto<S>(outz + d.plane_off, ost, o);
             }
           }
         }
@@ -853,9 +869,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
             f0 = fma(d.n[0], r, f0);
             f1 = fma(d.n[1], r, f1);
             f2 = fma(d.n[2], r, f2);
-            Tr::st(reinterpret_cast<S *>(reinterpret_cast<char *>(outz + d.plane_off / SZ) +
-                                         o0),
-                   Tr::kReduced ? o * d.inv_scale : o);
+            sto<S>(outz + d.plane_off, ost, Tr::kReduced ? o * d.inv_scale : o);
           }
         }
       }
