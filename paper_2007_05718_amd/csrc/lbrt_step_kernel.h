@@ -593,31 +593,34 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
   // read a clamped cell whose values are never stored or summed), so the
   // loads need no guard: a guarded load into a zeroed register would make
   // the compiler drain all outstanding memory operations at the zeroing.
+  // The loads take a uniform base (the plane's first cell, `cplane`) plus
+  // the lane's byte offset, made opaque per plane like the stores' below.
   T med[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-  auto load_medium = [&](int64_t c) {
-    med[0] = (T)ka[c];
-    med[1] = (T)ks[c];
-    med[2] = (T)eta[c];
+  const uint32_t ocell = o0 / (uint32_t)SZ;   // the lane's cell in a plane
+  auto load_medium = [&](int64_t cplane, uint32_t om) {
+    med[0] = (T)ldo<float>(ka + cplane, om);
+    med[1] = (T)ldo<float>(ks + cplane, om);
+    med[2] = (T)ldo<float>(eta + cplane, om);
     if constexpr (MOVING) {
-      med[3] = (T)vel[c];
-      med[4] = (T)vel[p.ncell + c];
-      med[5] = (T)vel[2 * p.ncell + c];
+      med[3] = (T)ldo<float>(vel + cplane, om);
+      med[4] = (T)ldo<float>(vel + p.ncell + cplane, om);
+      med[5] = (T)ldo<float>(vel + 2 * p.ncell + cplane, om);
     }
   };
-  load_medium((int64_t)zb * pc + (int64_t)(o0 / (uint32_t)SZ));
+  load_medium((int64_t)zb * pc, ocell * 4u);
 
   for (int z = zb; z < ze; ++z) {
     const int par = (z - zb) & 1;
     tb = tab + opaque(q * M);
     const int64_t cz = (int64_t)z * pc;
-    const int64_t cell = cz + (int64_t)(o0 / (uint32_t)SZ);
 
     // this plane's medium, loaded during the previous plane; the next
     // plane's goes out once the collision has used this one (the last plane
     // reloads its own cells)
     const T kat = med[0], kst = med[1], et = med[2];
     const T vx = med[3], vy = med[4], vz = med[5];
-    const int64_t cell_next = z + 1 < ze ? cell + pc : cell;
+    const int64_t cz_next = z + 1 < ze ? cz + pc : cz;
+    const uint32_t om = opaque_lane(ocell * 4u);
     T W = T(1), dtWk = T(0);
     if constexpr (MOVING) {
       W = T(1) / sqrt(T(1) - (vx * vx + vy * vy + vz * vz));
@@ -813,7 +816,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
         const T g = c * dt * kst * lam;
         be0 = g * Fn0; be1 = g * Fn1; be2 = g * Fn2;
       }
-      load_medium(cell_next);
+      load_medium(cz_next, om);
       issue_next();
       if (valid) {
         if (p.flags & KF_LAMZERO) {
@@ -873,7 +876,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
           }
         }
       }
-      load_medium(cell_next);
+      load_medium(cz_next, om);
       // Moments of the new state, combined like the streamed ones through the
       // other half of the double buffer.  It is free: its last readers were
       // the previous plane's, and every wave has passed this plane's barrier.
@@ -893,11 +896,16 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
 
     if (q == 0 && valid) {
       if (p.flags & KF_WRITE_EF) {
-        if (Eout) Eout[cell] = En;
+        // at a uniform base plus the lane's (opaque) byte offset, as above
+        const uint32_t oT = opaque_lane(ocell * (uint32_t)sizeof(T));
+        auto put = [&](T *base, T v) {
+          *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + oT) = v;
+        };
+        if (Eout) put(Eout + cz, En);
         if (Fout) {
-          Fout[cell] = Fn0;
-          Fout[p.ncell + cell] = Fn1;
-          Fout[2 * p.ncell + cell] = Fn2;
+          put(Fout + cz, Fn0);
+          put(Fout + p.ncell + cz, Fn1);
+          put(Fout + 2 * p.ncell + cz, Fn2);
         }
       }
       if (diag) {
