@@ -154,6 +154,14 @@ __device__ __forceinline__ void unroll(F &f) {
   }
 }
 
+// Element i of an inflow ghost plane.  The plane pointers come from a table
+// in device memory, where the compiler cannot see that they are global
+// memory; the cast makes the load a global one (a flat load would also wait
+// on the LDS/scalar counter).
+__device__ __forceinline__ float gload(const float *p, int64_t i) {
+  return ((const __attribute__((address_space(1))) float *)p)[i];
+}
+
 // w0 u + w1 v, in one fixed rounding order used by every path.
 template <typename T>
 __device__ __forceinline__ T lerp2(T w0, T w1, T u, T v) {
@@ -300,7 +308,7 @@ checked_P(const DirTab<typename StoreTraits<S>::T> &d, const S *__restrict__ pl,
       if (!ox && !oy) {
         val = Tr::ld(pl + (int64_t)cy * nx + cx);
       } else if (oy && !ox && gy != nullptr) {
-        const T gv = (T)gy[(int64_t)zl * nx + cx];
+        const T gv = (T)gload(gy, (int64_t)zl * nx + cx);
         val = Tr::kReduced ? gv * d.inv_scale : gv;
       }
     }
@@ -329,7 +337,7 @@ ghost_P(const DirTab<typename StoreTraits<S>::T> &d, const float *gz, int x, int
     if (pery) cy = wrap(cy, ny);
     T val = T(0);
     if ((unsigned)cx < (unsigned)nx && (unsigned)cy < (unsigned)ny) {
-      const T gv = (T)gz[(int64_t)cy * nx + cx];
+      const T gv = (T)gload(gz, (int64_t)cy * nx + cx);
       val = Tr::kReduced ? gv * d.inv_scale : gv;
     }
     v[b] = val;
@@ -345,16 +353,24 @@ ghost_P(const DirTab<typename StoreTraits<S>::T> &d, const float *gz, int x, int
 template <typename T>
 __device__ __forceinline__ T x_ghost_correction(const DirTab<T> &d, const float *gx, int y, int z,
                                                 int ny, int nz, int py, int pz) {
-  T acc = T(0);
+  // The four taps are loaded together (an out-of-range tap reads element 0
+  // and is skipped), so that they share one wait.
+  float g[4];
+  bool ok[4];
 #pragma unroll
-  for (int b = 1; b < 8; b += 2) {
+  for (int k = 0; k < 4; ++k) {
+    const int b = 2 * k + 1;
     int cy = y - ((b >> 1) & 1) * d.s[1];
     int cz = z - (b >> 2) * d.s[2];
     if (py) cy = wrap(cy, ny);
     if (pz) cz = wrap(cz, nz);
-    if ((unsigned)cy < (unsigned)ny && (unsigned)cz < (unsigned)nz)
-      acc = fma(d.tw[b], (T)gx[(int64_t)cz * ny + cy], acc);
+    ok[k] = (unsigned)cy < (unsigned)ny && (unsigned)cz < (unsigned)nz;
+    g[k] = gload(gx, ok[k] ? (int64_t)cz * ny + cy : 0);
   }
+  T acc = T(0);
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (ok[k]) acc = fma(d.tw[2 * k + 1], (T)g[k], acc);
   return acc;
 }
 
@@ -375,7 +391,7 @@ __device__ inline T ghost_influx(const DirTab<T> &d, const float *g, int a, int 
     if (per[0]) u = wrap(u, n3[0]);
     if (per[o2]) w = wrap(w, n3[o2]);
     if ((unsigned)u < (unsigned)n3[0] && (unsigned)w < (unsigned)n3[o2])
-      acc = fma(d.tw[b], (T)g[(int64_t)w * n3[0] + u], acc);
+      acc = fma(d.tw[b], (T)gload(g, (int64_t)w * n3[0] + u), acc);
   }
   return acc;
 }
@@ -685,9 +701,10 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
       };
       unroll<0, M>(body);
     }
-    if (p.flags & KF_XGHOSTS) {
+    if ((p.flags & KF_XGHOSTS) && xface_tile) {
       // Inflow ghosts on the x faces enter after the vacuum sums, slot by
-      // slot, for the face lanes of the directions with a ghost plane there.
+      // slot, for the face lanes of the directions with a ghost plane there
+      // (only tiles on a non-periodic x face have such lanes).
       auto body = [&]<int J>() {
         const DirTab<T> &d = tb[J];
         const float *gx = inflow->ghost[q * M + J][0];
