@@ -64,7 +64,7 @@ struct lbrt_ctx {
   bool inflow_valid = false;
   TileShape tile{64, 1};
   int zlen = 64;                  // z-planes per block of the main kernel
-  int zlen_general = 8;           // z-planes per block of the general kernel
+  int zlen_general = 4;           // z-planes per block of the general kernel
   // General-kernel tile lists (device, int4 per block), for calls without
   // (index 0) and with (index 1) inflow ghost planes on a z face.
   int4 *general_dev[2] = {nullptr, nullptr};
