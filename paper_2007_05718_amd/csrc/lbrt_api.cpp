@@ -51,6 +51,7 @@ struct lbrt_ctx {
   int bucket = 0;                 // index into kBuckets
   int nb = 0;                     // bucket size
   bool paired = false;
+  bool nwq_zero = false;          // every wave's sum of n_i w_i is exactly 0
   std::vector<int> order;         // processing index -> storage plane
   void *tab_dev = nullptr;        // DirTab<float> or DirTab<double>, nb entries
   size_t tab_bytes = 0;
@@ -207,6 +208,17 @@ void build_table(const lbrt_ctx &c, std::vector<DirTab<T>> &tab) {
   }
 }
 
+// True when every wave's sum of n_i w_i is exactly 0 (a centrally symmetric
+// rule whose antipodal pairs never straddle two waves): the kernels' FP64
+// reference term of the flux is then exactly 0 and is skipped.
+template <typename T>
+bool all_nwq_zero(const std::vector<DirTab<T>> &tab) {
+  for (const DirTab<T> &e : tab)
+    for (int a = 0; a < 3; ++a)
+      if (e.nwq[a] != 0.0) return false;
+  return true;
+}
+
 int ensure_partials(lbrt_ctx *c, int nblocks) {
   if (nblocks <= c->partials_cap) return LBRT_OK;
   if (c->partials) (void)hipFree(c->partials);
@@ -250,6 +262,7 @@ KParams make_params(const lbrt_ctx *c) {
   if (c->paired) p.flags |= KF_PAIRED;
   if (d.moving_fluid) p.flags |= KF_MOVING;
   if (d.lambda_aniso == 0.0) p.flags |= KF_LAMZERO;
+  if (c->nwq_zero) p.flags |= KF_NWQZERO;
   p.dt = d.dt;  // time step in length units (c = 1)
   p.lam = d.lambda_aniso;
   return p;
@@ -504,6 +517,7 @@ int lbrt_init(const lbrt_desc *d, lbrt_ctx **out) {
   if (d->storage == LBRT_FP64) {
     std::vector<DirTab<double>> tab;
     build_table(*c, tab);
+    c->nwq_zero = all_nwq_zero(tab);
     tab_bytes = sizeof(DirTab<double>) * tab.size();
     c->tab_bytes = tab_bytes;
     e = hipMalloc(&c->tab_dev, tab_bytes);
@@ -511,6 +525,7 @@ int lbrt_init(const lbrt_desc *d, lbrt_ctx **out) {
   } else {
     std::vector<DirTab<float>> tab;
     build_table(*c, tab);
+    c->nwq_zero = all_nwq_zero(tab);
     tab_bytes = sizeof(DirTab<float>) * tab.size();
     c->tab_bytes = tab_bytes;
     e = hipMalloc(&c->tab_dev, tab_bytes);

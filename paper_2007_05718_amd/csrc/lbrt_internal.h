@@ -80,6 +80,7 @@ enum : uint32_t {
   KF_WRITE_EF = 1u << 3, // write E, F of the new state
   KF_LAMZERO = 1u << 4,  // lambda == 0 (anisotropic term skipped)
   KF_XGHOSTS = 1u << 5,  // some inflow ghost plane sits on an x face
+  KF_NWQZERO = 1u << 6,  // every wave's sum of n_i w_i is exactly 0
 };
 
 struct KParams {
