@@ -65,31 +65,53 @@ adj_pull_kernel(const T *__restrict__ in, T *__restrict__ out, const DirTab<T> *
   const int64_t pc = (int64_t)p.nx * p.ny;
   const T *src = in + d.plane_el;
 
-  // value of the tap (cx, cy, cz) by the boundary rules
-  auto tap = [&](int cx, int cy, int cz) -> T {
-    int c[3] = {cx, cy, cz};
-    int nout = 0, oa = 0;
+  // Tap (cx, cy, cz) after periodic wrapping: its element index in the
+  // direction's plane when inside the box, else the axis it leaves along
+  // (oa) and how many axes it leaves along (nout).
+  struct Tap {
+    int c[3];
+    int nout, oa;
+  };
+  auto locate = [&](int cx, int cy, int cz) {
+    Tap t{{cx, cy, cz}, 0, 0};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      if (p.periodic[a]) c[a] = wrap(c[a], n3[a]);
-      if ((unsigned)c[a] >= (unsigned)n3[a]) {
-        ++nout;
-        oa = a;
+      if (p.periodic[a]) t.c[a] = wrap(t.c[a], n3[a]);
+      if ((unsigned)t.c[a] >= (unsigned)n3[a]) {
+        ++t.nout;
+        t.oa = a;
       }
     }
-    if (nout == 0) return src[(int64_t)c[2] * pc + (int64_t)c[1] * p.nx + c[0]];
-    if (REV || nout > 1 || ghost[oa] == nullptr) return T(0);
-    // face layouts: x faces [z][y], y faces [z][x], z faces [y][x]
-    const int64_t gi = oa == 0 ? (int64_t)c[2] * p.ny + c[1]
-                               : (oa == 1 ? (int64_t)c[2] * p.nx + c[0]
-                                          : (int64_t)c[1] * p.nx + c[0]);
-    return (T)ghost[oa][gi];
+    return t;
   };
-  // plane value P(zl): the x/y interpolation of the four taps of plane zl
+  // A tap outside the box: the face's inflow ghost value when it leaves
+  // along exactly one axis and that face has a ghost plane, else 0.
+  auto outside = [&](const Tap &t) -> T {
+    if (REV || t.nout > 1 || ghost[t.oa] == nullptr) return T(0);
+    // face layouts: x faces [z][y], y faces [z][x], z faces [y][x]
+    const int64_t gi = t.oa == 0 ? (int64_t)t.c[2] * p.ny + t.c[1]
+                                 : (t.oa == 1 ? (int64_t)t.c[2] * p.nx + t.c[0]
+                                              : (int64_t)t.c[1] * p.nx + t.c[0]);
+    return (T)gload(ghost[t.oa], gi);
+  };
+  // plane value P(zl): the x/y interpolation of the four taps of plane zl.
+  // The four in-box loads go out together (a tap outside the box reads
+  // element 0 and is replaced), so that a plane costs one wait, not four.
   auto plane = [&](int zl) -> T {
-    const T a0 = tap(x, y, zl), a1 = tap(x - sx, y, zl);
-    const T b0 = tap(x, y - sy, zl), b1 = tap(x - sx, y - sy, zl);
-    return interp4(d, a0, a1, b0, b1);
+    const Tap t[4] = {locate(x, y, zl), locate(x - sx, y, zl), locate(x, y - sy, zl),
+                      locate(x - sx, y - sy, zl)};
+    T v[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int64_t i = t[b].nout == 0
+                            ? (int64_t)t[b].c[2] * pc + (int64_t)t[b].c[1] * p.nx + t[b].c[0]
+                            : 0;
+      v[b] = src[i];
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if (t[b].nout != 0) v[b] = outside(t[b]);
+    return interp4(d, v[0], v[1], v[2], v[3]);
   };
   const T dz = d.delta[2], dz1 = T(1) - d.delta[2];
   // I*(z) = (1 - dz) P(z) + dz P(z - sz), marching up in z with one carried
