@@ -294,7 +294,12 @@ checked_P(const DirTab<typename StoreTraits<S>::T> &d, const S *__restrict__ pl,
           typename StoreTraits<S>::T &own) {
   using Tr = StoreTraits<S>;
   using T = typename Tr::T;
+  // The in-box loads of the four taps go out together (a tap outside the
+  // box, or of an invalid lane, reads element 0 of the plane and is
+  // replaced afterwards), so that a slot costs one wait, not four.
   T v[4];
+  int gx[4];
+  bool inb[4], yg[4];
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
     int cx = x - (b & 1) * d.s[0];
@@ -303,16 +308,21 @@ checked_P(const DirTab<typename StoreTraits<S>::T> &d, const S *__restrict__ pl,
     if (pery) cy = wrap(cy, ny);
     const bool ox = (unsigned)cx >= (unsigned)nx;
     const bool oy = (unsigned)cy >= (unsigned)ny;
-    T val = T(0);
-    if (valid) {
-      if (!ox && !oy) {
-        val = Tr::ld(pl + (int64_t)cy * nx + cx);
-      } else if (oy && !ox && gy != nullptr) {
-        const T gv = (T)gload(gy, (int64_t)zl * nx + cx);
+    inb[b] = valid && !ox && !oy;
+    yg[b] = valid && oy && !ox && gy != nullptr;
+    gx[b] = cx;
+    v[b] = Tr::ld(pl + (inb[b] ? (int64_t)cy * nx + cx : 0));
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    if (!inb[b]) {
+      T val = T(0);
+      if (yg[b]) {
+        const T gv = (T)gload(gy, (int64_t)zl * nx + gx[b]);
         val = Tr::kReduced ? gv * d.inv_scale : gv;
       }
+      v[b] = val;
     }
-    v[b] = val;
   }
   own = v[0];
   return interp4(d, v[0], v[1], v[2], v[3]);
