@@ -1,9 +1,10 @@
 // Fused stream-and-collide kernel for gfx950: a z-march over xy tiles.
 //
-// A block of 256 threads owns an xy tile of 64 cells (tx x ty, x fastest, one
-// cell per lane) and marches it through a range of z-planes.  Its four wave64s
-// split the directions: wave q streams the q-th quarter of the direction slots
-// for the tile's 64 cells and keeps the streamed values in registers.
+// A block owns an xy tile of 64 cells (tx x ty, x fastest, one cell per lane)
+// and marches it through a range of z-planes.  Its NW wave64s (8 for the
+// 112- and 152-slot buckets, 4 below) split the direction slots: wave q
+// streams the q-th share of the slots for the tile's 64 cells and keeps the
+// streamed values in registers.
 //
 // The trilinear pull of eq. (interp) is separable.  With the plane value
 //   P_i(x, y, z') = (1-dy)[(1-dx) I(x, y, z') + dx I(x-sx, y, z')]
@@ -17,23 +18,25 @@
 // lane's byte offset, so the address arithmetic is scalar.
 //
 // Per plane:
-//   stream   the quarter of the directions, P from 4 row loads, I* from P and
-//            the carried plane;
+//   stream   the wave's slots, P from 4 row loads (issued a few slots ahead),
+//            I* from P and the carried plane;
 //   moments  per-wave partial E*, F* (eq. moments_discrete), combined across
-//            the four waves through LDS in a fixed order;
+//            the waves through LDS in a fixed order;
 //   collide  per-cell closed form of the chosen collision (Sec. 3.3, App. B),
 //            evaluated by every wave;
-//   store    each wave its quarter of the new populations; wave 0 also E, F.
-// Energy diagnostics (sums of E and E*, the outflux through each face and the
-// influx from inflow ghosts) accumulate per lane over the march and end as
-// per-block partials in FP64.
+//   store    each wave its share of the new populations; wave 0 also E, F.
+// The next plane's medium and first taps go out between the collision and
+// the stores.  Energy diagnostics (sums of E and E*, the outflux through each
+// face and the influx from inflow ghosts) accumulate per lane over the march
+// and end as per-block partials in FP64.
 //
 // Boundaries: x faces are resolved per lane (the x-shifted load of a face lane
 // is re-targeted to the wrapped cell, or to its own cell and zeroed), planes
 // outside the box in z come from the inflow ghost plane or are vacuum, and
-// tiles whose y halo leaves the box (or with ragged lanes) take a per-tap
-// checked path.  Inflow ghosts on x faces enter through a separate correction
-// term after the vacuum sums, so every path computes the same value.
+// tiles whose y halo leaves the box take a per-tap checked path.  A ragged
+// last tile in x reads its row's last cell on its extra lanes.  Inflow
+// ghosts on x faces enter through a separate correction term after the
+// vacuum sums, so every path computes the same value.
 #pragma once
 
 #include <utility>
