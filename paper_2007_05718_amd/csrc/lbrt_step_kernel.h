@@ -468,6 +468,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
   constexpr int SZ = (int)sizeof(S);
   constexpr int M = NB / NW;
   static_assert(NB % NW == 0, "direction slots must split evenly over the waves");
+  static_assert(NB / NW <= 32, "a wave's slots must fit a 32-bit mask");
 
   const int nx = p.nx, ny = p.ny, nz = p.nz;
   const int64_t pc = (int64_t)nx * ny;   // cells per z-plane
@@ -566,6 +567,21 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
     return zl;
   };
   auto own_plane = [&](const DirTab<T> &d, int z) { return d.s[2] >= 0 || z + 1 < ze; };
+
+  // The slots of this wave with an inflow ghost plane on an x face that this
+  // tile touches (bit J for slot J; only tiles on a non-periodic x face), so
+  // that the plane loop tests one bit per slot instead of reading the slot's
+  // ghost pointer and shift sign from memory on every plane.
+  uint32_t xgmask = 0u;
+  if ((p.flags & KF_XGHOSTS) && xface_tile) {
+    const bool tlo = x0 == 0, thi = x0 + p.tx >= nx;
+    auto scan = [&]<int J>() {
+      const DirTab<T> &d = tab[q * M + J];
+      if (inflow->ghost[q * M + J][0] != nullptr && ((d.s[0] > 0 && tlo) || (d.s[0] < 0 && thi)))
+        xgmask |= 1u << J;
+    };
+    unroll<0, M>(scan);
+  }
 
   // Prologue: the carried plane of every slot (P at zb - 1 for sz > 0, at zb
   // for sz < 0; nothing for sz == 0).  On the main path a plane outside the
@@ -714,14 +730,13 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
       };
       unroll<0, M>(body);
     }
-    if ((p.flags & KF_XGHOSTS) && xface_tile) {
+    if (xgmask != 0u) {
       // Inflow ghosts on the x faces enter after the vacuum sums, slot by
-      // slot, for the face lanes of the directions with a ghost plane there
-      // (only tiles on a non-periodic x face have such lanes).
+      // slot, for the face lanes of the directions with a ghost plane there.
       auto body = [&]<int J>() {
         const DirTab<T> &d = tb[J];
         const float *gx = inflow->ghost[q * M + J][0];
-        if (gx != nullptr && (d.s[0] > 0 ? lox : (d.s[0] < 0 ? hix : false))) {
+        if (((xgmask >> J) & 1u) && (d.s[0] > 0 ? lox : hix)) {
           const T dI = x_ghost_correction<T>(d, gx, y, z, ny, nz, pery, perz);
           fin += (double)dI;
           Is[J] += dI;
