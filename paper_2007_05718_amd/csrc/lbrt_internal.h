@@ -113,6 +113,8 @@ constexpr int kDiag = LBRT_DIAG_LEN;
 // Per-block diagnostic partials of the step kernel: sum E, sum E*, outflux
 // through the faces -x, +x, -y, +y, -z, +z, influx from inflow ghosts.
 constexpr int kStepPartials = 9;
+// Direction groups of the z-face flux kernel (its grid's second dimension).
+constexpr int kZfaceGroups = 8;
 
 // Direction-count buckets with a compiled kernel (multiples of 8: four waves
 // times pairs).  Rules whose size is not a bucket run in the next larger

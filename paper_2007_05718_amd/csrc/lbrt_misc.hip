@@ -86,6 +86,9 @@ diag_reduce_kernel(const double *__restrict__ partials, int nblocks, double *__r
   // partial columns: 0 sum E, 1 sum E*, 2..7 outflux per face, 8 influx
   const int col = j == 0 ? 0 : (j == 8 ? 1 : (j == 7 ? 8 : j + 1));
   double s = 0.0;
+  // (unrolled so that several loads are in flight; the additions keep their
+  // order)
+#pragma unroll 8
   for (int b = threadIdx.x; b < nblocks; b += kBlock) s += partials[(int64_t)b * kStepPartials + col];
   red[threadIdx.x] = s;
   __syncthreads();
@@ -149,33 +152,37 @@ hipError_t launch_diag_reduce(const double *partials, int nblocks, double *diag,
   return hipGetLastError();
 }
 
+// Blocks of the z-face flux kernel: the face cells in blocks of kBlock, times
+// kZfaceGroups direction groups (each thread visits every kZfaceGroups-th
+// direction, so that the grid has enough waves to hide the loads' latency).
 int zface_blocks(const KParams &p) {
   if (p.periodic[2]) return 0;
-  return (int)((2 * (int64_t)p.nx * p.ny + kBlock - 1) / kBlock);
+  return (int)((2 * (int64_t)p.nx * p.ny + kBlock - 1) / kBlock) * kZfaceGroups;
 }
 
 hipError_t launch_zface(int storage, const void *I, const void *tab, const KParams &p,
                         const InflowArgs *inflow, double *partials, hipStream_t s) {
-  const int nb = zface_blocks(p);
+  const int nb = zface_blocks(p) / kZfaceGroups;
   if (nb == 0) return hipSuccess;
+  const dim3 grid(nb, kZfaceGroups);
   switch (storage) {
     case LBRT_FP32:
-      hipLaunchKernelGGL(zface_kernel<float>, dim3(nb), dim3(kBlock), 0, s,
+      hipLaunchKernelGGL(zface_kernel<float>, grid, dim3(kBlock), 0, s,
                          static_cast<const float *>(I), static_cast<const DirTab<float> *>(tab),
                          p, inflow, partials);
       break;
     case LBRT_FP64:
-      hipLaunchKernelGGL(zface_kernel<double>, dim3(nb), dim3(kBlock), 0, s,
+      hipLaunchKernelGGL(zface_kernel<double>, grid, dim3(kBlock), 0, s,
                          static_cast<const double *>(I),
                          static_cast<const DirTab<double> *>(tab), p, inflow, partials);
       break;
     case LBRT_BF16:
-      hipLaunchKernelGGL(zface_kernel<bf16_t>, dim3(nb), dim3(kBlock), 0, s,
+      hipLaunchKernelGGL(zface_kernel<bf16_t>, grid, dim3(kBlock), 0, s,
                          static_cast<const bf16_t *>(I), static_cast<const DirTab<float> *>(tab),
                          p, inflow, partials);
       break;
     default:
-      hipLaunchKernelGGL(zface_kernel<f16_t>, dim3(nb), dim3(kBlock), 0, s,
+      hipLaunchKernelGGL(zface_kernel<f16_t>, grid, dim3(kBlock), 0, s,
                          static_cast<const f16_t *>(I), static_cast<const DirTab<float> *>(tab),
                          p, inflow, partials);
       break;

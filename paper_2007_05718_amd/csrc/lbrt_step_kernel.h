@@ -1038,6 +1038,7 @@ zface_kernel(const S *__restrict__ I, const DirTab<typename StoreTraits<S>::T> *
   const int nx = p.nx, ny = p.ny, nz = p.nz;
   const int64_t pc = (int64_t)nx * ny;
   const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;   // over 2 pc
+  const int g = blockIdx.y;   // direction group: directions g, g + G, ...
   double v[kStepPartials];
 #pragma unroll
   for (int j = 0; j < kStepPartials; ++j) v[j] = 0.0;
@@ -1049,7 +1050,7 @@ zface_kernel(const S *__restrict__ I, const DirTab<typename StoreTraits<S>::T> *
     const bool lox = !p.periodic[0] && x == 0, hix = !p.periodic[0] && x == nx - 1;
     const bool loy = !p.periodic[1] && y == 0, hiy = !p.periodic[1] && y == ny - 1;
     T out = T(0), in = T(0);
-    for (int i = 0; i < p.ndir; ++i) {
+    for (int i = g; i < p.ndir; i += (int)gridDim.y) {
       const DirTab<T> &d = tab[i];
       const int sz = d.s[2];
       if (sz != 0 && (sz > 0) == (face == 1)) {
@@ -1067,7 +1068,8 @@ zface_kernel(const S *__restrict__ I, const DirTab<typename StoreTraits<S>::T> *
     v[6 + face] = (double)out;
     v[8] = (double)in;
   }
-  block_sums<kStepPartials>(v, partials + (int64_t)blockIdx.x * kStepPartials);
+  block_sums<kStepPartials>(
+      v, partials + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * kStepPartials);
 }
 
 template <typename S, int NB, bool MOVING>
