@@ -210,7 +210,8 @@ void build_table(const lbrt_ctx &c, std::vector<DirTab<T>> &tab) {
 
 // True when every wave's sum of n_i w_i is exactly 0 (a centrally symmetric
 // rule whose antipodal pairs never straddle two waves): the kernels' FP64
-// reference term of the flux is then exactly 0 and is skipped.
+// reference term of the flux is then exactly 0 and is skipped (unless
+// LBRT_FP64_FLUX_TERM is set, which keeps it: the same bits, for checking).
 template <typename T>
 bool all_nwq_zero(const std::vector<DirTab<T>> &tab) {
   for (const DirTab<T> &e : tab)
@@ -517,7 +518,7 @@ int lbrt_init(const lbrt_desc *d, lbrt_ctx **out) {
   if (d->storage == LBRT_FP64) {
     std::vector<DirTab<double>> tab;
     build_table(*c, tab);
-    c->nwq_zero = all_nwq_zero(tab);
+    c->nwq_zero = all_nwq_zero(tab) && !std::getenv("LBRT_FP64_FLUX_TERM");
     tab_bytes = sizeof(DirTab<double>) * tab.size();
     c->tab_bytes = tab_bytes;
     e = hipMalloc(&c->tab_dev, tab_bytes);
@@ -525,7 +526,7 @@ int lbrt_init(const lbrt_desc *d, lbrt_ctx **out) {
   } else {
     std::vector<DirTab<float>> tab;
     build_table(*c, tab);
-    c->nwq_zero = all_nwq_zero(tab);
+    c->nwq_zero = all_nwq_zero(tab) && !std::getenv("LBRT_FP64_FLUX_TERM");
     tab_bytes = sizeof(DirTab<float>) * tab.size();
     c->tab_bytes = tab_bytes;
     e = hipMalloc(&c->tab_dev, tab_bytes);

@@ -52,11 +52,13 @@ def upload_fields(prob):
 
 
 def run_problem(prob, storage=None, steps=None, I0=None, want_diag=True, collision=None,
-                tile=None, zlen=None, zlen_general=None):
+                tile=None, zlen=None, zlen_general=None, fp64_flux_term=None):
     """Run ``steps`` GPU steps; returns dict with float64 numpy I (decoded),
     E, F, diag and the oracle's starting state ``I0_eff``.  ``tile``
     ("TXxTY"), ``zlen`` and ``zlen_general`` override the context's tiling
-    (they change which cells take which kernel path, never the results)."""
+    (they change which cells take which kernel path, never the results);
+    ``fp64_flux_term`` keeps the FP64 reference term of the flux sums even
+    where it is exactly 0 (the results must not change either)."""
     import os
     torch = torch_mod()
     L = lib()
@@ -66,7 +68,8 @@ def run_problem(prob, storage=None, steps=None, I0=None, want_diag=True, collisi
     if collision is not None:
         kw["collision"] = collision
     desc = L.Desc.from_problem(prob, storage=storage, **kw)
-    env = {"LBRT_TILE": tile, "LBRT_ZLEN": zlen, "LBRT_ZLEN_GENERAL": zlen_general}
+    env = {"LBRT_TILE": tile, "LBRT_ZLEN": zlen, "LBRT_ZLEN_GENERAL": zlen_general,
+           "LBRT_FP64_FLUX_TERM": 1 if fp64_flux_term else None}
     old = {k: os.environ.get(k) for k in env}
     for k, v in env.items():
         if v is not None:

@@ -35,6 +35,24 @@ def test_diffusion_128_one_step_matches_oracle():
     assert eF < 1e-5
 
 
+def test_skipped_fp64_flux_term_gives_the_same_bits():
+    """The 50- and 110-point rules' antipodal pairs never straddle two waves,
+    so each wave's sum of n_i w_i is exactly 0 and the kernels skip the FP64
+    reference term of the flux sums; keeping it must give the same bits
+    (also in thick cells, where the flux is a small difference of terms of
+    size E)."""
+    probs = (wl.diffusion(n=32), wl.random_problem(61, shape=(10, 12, 70), npoints=110, steps=3))
+    for prob, st in ((probs[0], gh.lib().LBRT_FP32), (probs[0], gh.lib().LBRT_BF16),
+                     (probs[1], gh.lib().LBRT_FP32)):
+        print(prob.name, prob.shape, prob.ndir, st, flush=True)
+        a = gh.run_problem(prob, storage=st, steps=3)
+        b = gh.run_problem(prob, storage=st, steps=3, fp64_flux_term=True)
+        gh.torch_mod().cuda.synchronize()
+        assert gh.torch_mod().equal(a["raw"], b["raw"]), st
+        assert np.array_equal(a["E"], b["E"]) and np.array_equal(a["F"], b["F"]), st
+        assert np.array_equal(a["diag"], b["diag"]), st
+
+
 def test_diffusion_128_full_run_follows_moment_recursion():
     torch = gh.torch_mod()
     L = gh.lib()
