@@ -130,7 +130,12 @@ int lbrt_validate(const lbrt_desc *desc);
 
 /* Validate, then build a context on the current HIP device: direction and
  * stencil tables in device memory, a small reduction buffer for the
- * diagnostics, kernel selection.  *out is set only on success. */
+ * diagnostics, kernel selection.  *out is set only on success.
+ * Environment variables read here change speed only, never results:
+ * LBRT_TILE ("TXxTY", tx * ty = 64) and LBRT_ZLEN, LBRT_ZLEN_GENERAL (z-range
+ * lengths) set the initial tiling (see lbrt_set_tiling); LBRT_FP64_FLUX_TERM
+ * (any value) keeps the FP64 reference term of the per-cell flux sums where
+ * it is exactly zero (rules whose antipodal pairs share a wave). */
 int lbrt_init(const lbrt_desc *desc, lbrt_ctx **out);
 
 /* Free the context's device tables.  NULL is accepted. */
