@@ -161,6 +161,11 @@ void lbrt_destroy(lbrt_ctx *ctx);
  *            [7] energy streamed in from inflow ghosts, summed over steps,
  *            [8] sum over cells of the streamed E* of the last step.
  *            diag is overwritten by the call.
+ * The call enqueues kernels only (the ghost-plane table is written by a
+ * kernel from the call's arguments), so it can be captured in a HIP graph,
+ * except for a call with diag that first grows the context's partials
+ * buffer (one hipMalloc when the tiling needs more rows than lbrt_init
+ * sized).
  */
 int lbrt_step(lbrt_ctx *ctx, void *I_a, void *I_b,
               const float *kappa_a, const float *kappa_s, const float *eta,
@@ -226,12 +231,13 @@ int lbrt_get_tiling(const lbrt_ctx *ctx, int32_t *tx, int32_t *ty, int32_t *zlen
  * diagnostics or inflow ghosts; E, F (or NULL) receive its moments after the
  * last step.  Every domain must share the storage type, the direction bucket
  * and the fluid kind of the first; supported: FP32 storage, static fluid.
- * Step s of the batch is one kernel launch over every tile of every domain
- * still running at step s, so small domains fill the GPU together.
+ * Step s of the batch is two kernel launches (boundary tiles, then interior
+ * tiles) over every tile of every domain still running at step s, so small
+ * domains fill the GPU together.
  *
  * lbrt_batch_create builds the tile lists on the host and uploads them (call
  * it outside graph capture); the domains' contexts and buffers must outlive
- * the batch.  lbrt_step_batched only enqueues kernels (one per step of the
+ * the batch.  lbrt_step_batched only enqueues kernels (two per step of the
  * longest domain) and may be captured in a hipGraph and replayed as one.
  */
 typedef struct {

@@ -429,21 +429,45 @@ def step_cells(I: np.ndarray, prob, cells: np.ndarray, collision=None) -> np.nda
 # Adjoint of a run (gradient of a detected energy)
 # ---------------------------------------------------------------------------
 def detector_weights(prob, face: int = FACE_PX) -> np.ndarray:
-    """Weights d with L(I) = sum d * I for the energy that crosses ``face``
-    in one streaming step, counted on the box's last layer of cells:
-    d_i(cell) = dt |n_i^a| / dx for directions leaving through the face and
-    cells on it, 0 elsewhere."""
+    """Weights d with L(I) = sum d * I for the energy that one streaming step
+    carries out through ``face`` (the face entry of ``boundary_fluxes``).
+
+    By eq. (interp) a population on a face cell sends the fraction
+    dt |n_i^a| / dx across the face of axis a it points out of.  A corner or
+    edge cell can send energy out along several axes; such energy is booked
+    on the first of them in the order x, y, z (the reading used for the face
+    fluxes).  So the weight on face axis a is dt |n_i^a| / dx times
+    (1 - dt |n_i^b| / dx) for every earlier axis b whose face the cell also
+    leaves through (non-periodic b), and 0 off the face or for directions
+    that do not leave through it."""
     axis = {FACE_MX: 2, FACE_PX: 2, FACE_MY: 1, FACE_PY: 1, FACE_MZ: 0, FACE_PZ: 0}[face]
-    comp = {2: 0, 1: 1, 0: 2}[axis]
-    size = (prob.nz, prob.ny, prob.nx)[axis]
+    sizes = (prob.nz, prob.ny, prob.nx)
+    comp_of_axis = {2: 0, 1: 1, 0: 2}          # array axis -> component of n
     d = np.zeros((prob.ndir, prob.nz, prob.ny, prob.nx))
-    layer = [slice(None)] * 3
-    layer[axis] = 0 if face % 2 == 0 else size - 1
+    if prob.bc[face] == BC_PERIODIC:
+        return d
+    coords = np.meshgrid(np.arange(prob.nz), np.arange(prob.ny), np.arange(prob.nx),
+                         indexing="ij")
     for i in range(prob.ndir):
-        nc = prob.dirs[i, comp]
+        n_i = prob.dirs[i]
+        nc = n_i[comp_of_axis[axis]]
         leaving = nc < 0 if face % 2 == 0 else nc > 0
-        if leaving:
-            d[(i,) + tuple(layer)] = prob.dt * abs(nc) / prob.dx
+        if not leaving:
+            continue
+        on_face = coords[axis] == (0 if face % 2 == 0 else sizes[axis] - 1)
+        wgt = np.where(on_face, prob.dt * abs(nc) / prob.dx, 0.0)
+        for b in (2, 1, 0):                    # earlier axes in the order x, y, z
+            if b == axis:
+                break
+            lo, hi = _AXIS_FACES[b]
+            if prob.bc[lo] == BC_PERIODIC:
+                continue
+            nb = n_i[comp_of_axis[b]]
+            if nb == 0.0:
+                continue
+            out_b = coords[b] == (sizes[b] - 1 if nb > 0 else 0)
+            wgt = np.where(out_b, wgt * (1.0 - prob.dt * abs(nb) / prob.dx), wgt)
+        d[i] = wgt
     return d
 
 

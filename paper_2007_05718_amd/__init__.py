@@ -18,9 +18,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# LBRT_LIBRARY names another build of the same library (e.g. one compiled
-# with different tuning macros); the default is the in-tree build.
-LIB_PATH = os.environ.get("LBRT_LIBRARY") or os.path.join(_HERE, "_lib", "liblbrt.so")
+LIB_PATH = os.path.join(_HERE, "_lib", "liblbrt.so")
 
 LBRT_OK, LBRT_E_INVAL, LBRT_E_CFL, LBRT_E_QUAD = 0, -1, -2, -3
 LBRT_E_NOMEM, LBRT_E_HIP, LBRT_E_UNSUPPORTED = -4, -5, -6
@@ -245,15 +243,25 @@ def _moment_dtype(storage: int):
     return torch.float64 if storage == LBRT_FP64 else torch.float32
 
 
-def _inflow_planes(inflow):
+def _face_plane_size(desc: "Desc", face: int) -> int:
+    """Elements of an inflow ghost plane on ``face`` (layouts of lbrt.h:
+    x faces [z][y], y faces [z][x], z faces [y][x])."""
+    nx, ny, nz = desc.c.nx, desc.c.ny, desc.c.nz
+    return {0: nz * ny, 1: nz * nx, 2: ny * nx}[int(face) >> 1]
+
+
+def _inflow_planes(desc: "Desc", inflow):
     if not inflow:
         return None, 0
     nin = len(inflow)
     planes = (lbrt_inflow * nin)()
     for j, (face, direction, vals) in enumerate(inflow):
+        if not 0 <= int(face) <= 5:
+            raise ValueError(f"inflow[{j}]: face {face} outside [0, 5]")
         planes[j].face = int(face)
         planes[j].dir = int(direction)
-        planes[j].values = _ptr(vals, f"inflow[{j}]", dtype=_torch().float32).value
+        planes[j].values = _ptr(vals, f"inflow[{j}]", _face_plane_size(desc, face),
+                                dtype=_torch().float32).value
     return planes, nin
 
 
@@ -264,7 +272,7 @@ def lbrt_step(ctx: Context, I_a, I_b, kappa_a, kappa_s, eta, vel=None, inflow=No
     d = ctx.desc
     n, nc = d.ndir, d.ncell
     st = d.c.storage
-    planes, nin = _inflow_planes(inflow)
+    planes, nin = _inflow_planes(d, inflow)
     f32 = _torch().float32
     rc = _lib.lbrt_step(
         ctx.handle, _ptr(I_a, "I_a", n * nc, _pop_dtype(st)),
@@ -284,7 +292,7 @@ def lbrt_adjoint_step(ctx: Context, I_n, lam_next, lam_out, detector_face: int, 
     d = ctx.desc
     n, nc = d.ndir, d.ncell
     st = d.c.storage
-    planes, nin = _inflow_planes(inflow)
+    planes, nin = _inflow_planes(d, inflow)
     f32 = _torch().float32
     gdt = _moment_dtype(st)
     _check(_lib.lbrt_adjoint_step(

@@ -8,8 +8,10 @@
 //   nu      = (dC/dI*)^T lambda',          (per cell, N directions)
 //   lambda  = d + S^T nu,                  (S^T: the pull from downwind cells)
 //   g_k    += (dC/dk)^T lambda'            for k = kappa_a, kappa_s, eta,
-// d being the detector weights of the face (the fraction dt |n^a| / dx of a
-// population that leaves through it, on the face's cells).
+// d being the detector weights of the face: on the face's cells, the
+// fraction of a population that the forward step books as outflux through
+// that face (dt |n^a| / dx, reduced on edges and corners where part of it
+// is booked on an earlier face in the order x, y, z).
 //
 // Per cell, with D_i = 1 - v.n_i, a_i = 1/(1 + dt W D_i (ka + ks)),
 // c_i = dt w_i / (W^3 D_i^3), B = (dt/W) sum w_i a_i / D_i and
@@ -117,15 +119,26 @@ adj_pull_kernel(const T *__restrict__ in, T *__restrict__ out, const DirTab<T> *
   // I*(z) = (1 - dz) P(z) + dz P(z - sz), marching up in z with one carried
   // plane value: P(z - 1) when sz > 0, P(z) when sz < 0
   T carry = sz > 0 ? plane(zb - 1) : (sz < 0 ? plane(zb) : T(0));
-  // detector: the cells on `face` for a direction that leaves through it
+  // detector: the cells on `face` for a direction that leaves through it.
+  // The weight is the fraction of the population that the forward step
+  // books on that face (the step kernels' rule): dt |n^a| / dx, times
+  // (1 - dt |n^b| / dx) for each earlier axis b (order x, y, z) whose
+  // non-periodic face the cell also leaves through.
   bool det = false;
   T dw = T(0);
+  const int c3[2] = {x, y};
   if (REV && face >= 0) {
     const int a = face >> 1;
     const bool hi = (face & 1) != 0;
     const bool leaves = hi ? d.s[a] > 0 : d.s[a] < 0;
     det = leaves && !p.periodic[a];
     dw = d.delta[a];
+    // the earlier axes (x, and y for a z face) are fixed per thread
+    for (int b = 0; b < a && b < 2; ++b) {
+      const bool out_b = !p.periodic[b] && ((d.s[b] > 0 && c3[b] == n3[b] - 1) ||
+                                            (d.s[b] < 0 && c3[b] == 0));
+      if (out_b) dw *= T(1) - d.delta[b];
+    }
   }
   for (int z = zb; z < ze; ++z) {
     T v;

@@ -60,9 +60,8 @@ struct lbrt_ctx {
   double *partials = nullptr;     // per-block sums of the step kernel
   int partials_cap = 0;
   InflowArgs *inflow_dev = nullptr; // ghost-plane table of the current call
+  bool any_inflow_face = false;     // some face is LBRT_BC_INFLOW
   void *adj_work = nullptr;         // one state: the adjoint's nu buffer
-  InflowArgs inflow_host{};         // what inflow_dev holds
-  bool inflow_valid = false;
   TileShape tile{64, 1};
   int zlen = 64;                  // z-planes per block of the main kernel
   int zlen_general = 4;           // z-planes per block of the general kernel
@@ -316,9 +315,10 @@ int plan_tiles(lbrt_ctx *c, int variant, bool zlo_inflow, bool zhi_inflow) {
   return LBRT_OK;
 }
 
-// Checks the inflow planes of a call and fills the per-slot ghost table.
-int build_inflow(const lbrt_ctx *c, const lbrt_inflow *inflow, int32_t ninflow, InflowArgs &in,
-                 bool &xghosts, bool &zghosts) {
+// Checks the inflow planes of a call and fills the compact per-slot ghost
+// table (which inflow_table_kernel expands into InflowArgs on the device).
+int build_inflow(const lbrt_ctx *c, const lbrt_inflow *inflow, int32_t ninflow,
+                 InflowCompact &in, bool &xghosts, bool &zghosts) {
   const lbrt_desc &d = c->desc;
   if (ninflow < 0 || ninflow > LBRT_MAX_INFLOW)
     return fail(LBRT_E_INVAL, "ninflow = %d outside [0, %d]", ninflow, (int)LBRT_MAX_INFLOW);
@@ -348,7 +348,7 @@ int build_inflow(const lbrt_ctx *c, const lbrt_inflow *inflow, int32_t ninflow, 
   }
   // per processing slot and axis: the ghost plane that slot pulls from
   for (int k = 0; k < LBRT_MAX_DIRS; ++k)
-    for (int a = 0; a < 3; ++a) in.ghost[k][a] = nullptr;
+    for (int a = 0; a < 3; ++a) in.slot_plane[k][a] = -1;
   xghosts = zghosts = false;
   for (int j = 0; j < ninflow; ++j) {
     xghosts |= (in.face[j] >> 1) == 0;
@@ -361,26 +361,115 @@ int build_inflow(const lbrt_ctx *c, const lbrt_inflow *inflow, int32_t ninflow, 
       if (comp == 0.0) continue;
       const int face = 2 * a + (comp > 0.0 ? 0 : 1);
       for (int j = 0; j < ninflow; ++j)
-        if (in.face[j] == face && in.dir[j] == i) in.ghost[k][a] = in.ptr[j];
+        if (in.face[j] == face && in.dir[j] == i) in.slot_plane[k][a] = (int8_t)j;
     }
   }
   return LBRT_OK;
 }
 
-// Sends the ghost table to the device, in stream order, only when it differs
-// from the previous call's (pageable source: the host copy may change right
-// after the call).
-int upload_inflow(lbrt_ctx *c, const InflowArgs &in, hipStream_t s) {
-  if (!c->inflow_valid || std::memcmp(&c->inflow_host, &in, sizeof(in)) != 0) {
-    hipError_t e0 = hipMemcpyAsync(c->inflow_dev, &in, sizeof(in), hipMemcpyHostToDevice, s);
-    if (e0 != hipSuccess) return hip_fail(e0, "uploading the inflow table");
-    c->inflow_host = in;
-    c->inflow_valid = true;
+int total_partials(const KParams &p) { return p.nblocks + p.ngeneral + zface_blocks(p); }
+
+// What a step call needs after its arguments are checked: the kernel
+// parameters (tile plan for the call's ghost planes) and the compact ghost
+// table.
+struct StepCall {
+  KParams p;
+  InflowCompact in;
+  StepLauncher launch;
+};
+
+int prepare_step(lbrt_ctx *c, void *I_a, void *I_b, const float *kappa_a, const float *kappa_s,
+                 const float *eta, const float *vel, const lbrt_inflow *inflow, int32_t ninflow,
+                 int32_t nsteps, StepCall &call) {
+  if (!c) return fail(LBRT_E_INVAL, "ctx is NULL");
+  if (nsteps < 0) return fail(LBRT_E_INVAL, "nsteps = %d < 0", nsteps);
+  if (!I_a || !I_b) return fail(LBRT_E_INVAL, "population buffers are required");
+  if (I_a == I_b) return fail(LBRT_E_INVAL, "I_a and I_b must be distinct (ping-pong)");
+  const lbrt_desc &d = c->desc;
+  const int64_t ncell = (int64_t)d.nx * d.ny * d.nz;
+  const size_t bytes = storage_bytes(d.storage) * (size_t)ncell * d.ndir;
+  const char *a = static_cast<const char *>(I_a), *b = static_cast<const char *>(I_b);
+  if (a < b + bytes && b < a + bytes) return fail(LBRT_E_INVAL, "I_a and I_b overlap");
+  if (!kappa_a || !kappa_s || !eta) return fail(LBRT_E_INVAL, "kappa_a, kappa_s, eta required");
+  if (d.moving_fluid && !vel) return fail(LBRT_E_INVAL, "moving fluid: vel is required");
+  if (!d.moving_fluid && vel) return fail(LBRT_E_INVAL, "vel given but moving_fluid is off");
+  bool xghosts, zghosts;
+  int rc = build_inflow(c, inflow, ninflow, call.in, xghosts, zghosts);
+  if (rc != LBRT_OK) return rc;
+  KParams &p = call.p;
+  p = make_params(c);
+  if (xghosts) p.flags |= KF_XGHOSTS;
+  if (zghosts) {
+    // z ranges next to an inflow z face go to the general kernel
+    p.main_zr0 = c->main_zr0[1];
+    p.main_nzr = c->main_nzr[1];
+    p.nblocks = p.ntx * p.main_nty * p.main_nzr;
+    p.ngeneral = c->ngeneral[1];
+    p.general_list = c->general_dev[1];
+  }
+  call.launch = step_launcher(d.storage, c->bucket, d.moving_fluid != 0);
+  if (!call.launch)
+    return fail(LBRT_E_UNSUPPORTED, "no kernel for storage %d, %d directions", d.storage,
+                d.ndir);
+  return LBRT_OK;
+}
+
+int moments_impl(lbrt_ctx *c, const void *I, void *E, void *F, hipStream_t s);
+
+// The launches of a step call: the ghost table (when the context has an
+// inflow face, or always with `table_always`), the diagnostics clear, then
+// per step the z-face fluxes, the step kernels and the diagnostics
+// reduction.  `partials` holds total_partials(p) rows when diag is given.
+int run_steps(lbrt_ctx *c, const StepCall &call, void *I_a, void *I_b, const float *kappa_a,
+              const float *kappa_s, const float *eta, const float *vel, int32_t nsteps, void *E,
+              void *F, double *diag, double *partials, InflowArgs *table, bool table_always,
+              hipStream_t s) {
+  const lbrt_desc &d = c->desc;
+  const KParams &p = call.p;
+  hipError_t e;
+  if (table_always || c->any_inflow_face) {
+    e = launch_inflow_table(call.in, table, s);
+    if (e != hipSuccess) return hip_fail(e, "lbrt_step: writing the inflow table");
+  }
+  if (diag) {
+    e = launch_fill_f64(diag, kDiag, 0.0, s);
+    if (e != hipSuccess) return hip_fail(e, "lbrt_step: clearing diag");
+  }
+  if (nsteps == 0) {
+    if (E || F) return moments_impl(c, I_a, E, F, s);
+    return LBRT_OK;
+  }
+  const int nparts = total_partials(p);
+  for (int k = 0; k < nsteps; ++k) {
+    const void *src = (k & 1) ? I_b : I_a;
+    void *dst = (k & 1) ? I_a : I_b;
+    KParams pk = p;
+    const bool last = k == nsteps - 1;
+    if (diag) {
+      pk.flags |= KF_DIAG;
+      e = launch_zface(d.storage, src, c->tab_dev, p, table,
+                       partials + (size_t)(p.nblocks + p.ngeneral) * kStepPartials, s);
+      if (e != hipSuccess) return hip_fail(e, "lbrt_step: launching the z-face flux kernel");
+    }
+    if (last && (E || F)) pk.flags |= KF_WRITE_EF;
+    e = call.launch(src, dst, kappa_a, kappa_s, eta, vel, c->tab_dev, pk, table,
+                    last ? E : nullptr, last ? F : nullptr, partials, s);
+    if (e != hipSuccess) return hip_fail(e, "lbrt_step: launching the step kernel");
+    if (diag) {
+      e = launch_diag_reduce(partials, nparts, diag, k == 0, s);
+      if (e != hipSuccess) return hip_fail(e, "lbrt_step: reducing diagnostics");
+    }
   }
   return LBRT_OK;
 }
 
-int total_partials(const KParams &p) { return p.nblocks + p.ngeneral + zface_blocks(p); }
+int moments_impl(lbrt_ctx *c, const void *I, void *E, void *F, hipStream_t s) {
+  if (!E && !F) return LBRT_OK;
+  KParams p = make_params(c);
+  hipError_t e = launch_moments(c->desc.storage, I, c->tab_dev, p, E, F, s);
+  if (e != hipSuccess) return hip_fail(e, "lbrt_moments");
+  return LBRT_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -554,9 +643,16 @@ int lbrt_init(const lbrt_desc *d, lbrt_ctx **out) {
   KParams p = make_params(c);
   rc = ensure_partials(c, total_partials(p));
   if (rc == LBRT_OK) {
+    // the ghost table starts empty; calls on a context with an inflow face
+    // rewrite it on their stream
+    InflowArgs none;
+    std::memset(&none, 0, sizeof(none));
     e = hipMalloc(&c->inflow_dev, sizeof(InflowArgs));
-    if (e != hipSuccess) rc = fail(LBRT_E_NOMEM, "hipMalloc(context buffers): %s", hipGetErrorString(e));
+    if (e == hipSuccess)
+      e = hipMemcpy(c->inflow_dev, &none, sizeof(InflowArgs), hipMemcpyHostToDevice);
+    if (e != hipSuccess) rc = fail(LBRT_E_NOMEM, "context buffers: %s", hipGetErrorString(e));
   }
+  for (int f = 0; f < 6; ++f) c->any_inflow_face |= d->bc[f] == LBRT_BC_INFLOW;
   if (rc != LBRT_OK) {
     lbrt_destroy(c);
     return rc;
@@ -580,71 +676,16 @@ void lbrt_destroy(lbrt_ctx *c) {
 int lbrt_step(lbrt_ctx *c, void *I_a, void *I_b, const float *kappa_a, const float *kappa_s,
               const float *eta, const float *vel, const lbrt_inflow *inflow, int32_t ninflow,
               int32_t nsteps, void *E, void *F, double *diag, void *stream) {
-  if (!c) return fail(LBRT_E_INVAL, "ctx is NULL");
-  if (nsteps < 0) return fail(LBRT_E_INVAL, "nsteps = %d < 0", nsteps);
-  if (!I_a || !I_b) return fail(LBRT_E_INVAL, "population buffers are required");
-  if (I_a == I_b) return fail(LBRT_E_INVAL, "I_a and I_b must be distinct (ping-pong)");
-  const lbrt_desc &d = c->desc;
-  const int64_t ncell = (int64_t)d.nx * d.ny * d.nz;
-  const size_t bytes = storage_bytes(d.storage) * (size_t)ncell * d.ndir;
-  const char *a = static_cast<const char *>(I_a), *b = static_cast<const char *>(I_b);
-  if (a < b + bytes && b < a + bytes) return fail(LBRT_E_INVAL, "I_a and I_b overlap");
-  if (!kappa_a || !kappa_s || !eta) return fail(LBRT_E_INVAL, "kappa_a, kappa_s, eta required");
-  if (d.moving_fluid && !vel) return fail(LBRT_E_INVAL, "moving fluid: vel is required");
-  if (!d.moving_fluid && vel) return fail(LBRT_E_INVAL, "vel given but moving_fluid is off");
-  InflowArgs in;
-  bool xghosts, zghosts;
-  int rc0 = build_inflow(c, inflow, ninflow, in, xghosts, zghosts);
-  if (rc0 != LBRT_OK) return rc0;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  KParams p = make_params(c);
-  if (xghosts) p.flags |= KF_XGHOSTS;
-  if (zghosts) {
-    // z ranges next to an inflow z face go to the general kernel
-    p.main_zr0 = c->main_zr0[1];
-    p.main_nzr = c->main_nzr[1];
-    p.nblocks = p.ntx * p.main_nty * p.main_nzr;
-    p.ngeneral = c->ngeneral[1];
-    p.general_list = c->general_dev[1];
-  }
-  int rc = ensure_partials(c, total_partials(p));
+  StepCall call;
+  int rc = prepare_step(c, I_a, I_b, kappa_a, kappa_s, eta, vel, inflow, ninflow, nsteps, call);
   if (rc != LBRT_OK) return rc;
-  rc = upload_inflow(c, in, s);
-  if (rc != LBRT_OK) return rc;
-  StepLauncher launch = step_launcher(d.storage, c->bucket, d.moving_fluid != 0);
-  if (!launch) return fail(LBRT_E_UNSUPPORTED, "no kernel for storage %d, %d directions",
-                           d.storage, d.ndir);
-  hipError_t e;
   if (diag) {
-    e = launch_fill_f64(diag, kDiag, 0.0, s);
-    if (e != hipSuccess) return hip_fail(e, "lbrt_step: clearing diag");
+    rc = ensure_partials(c, total_partials(call.p));
+    if (rc != LBRT_OK) return rc;
   }
-  if (nsteps == 0) {
-    if (E || F) return lbrt_moments(c, I_a, E, F, stream);
-    return LBRT_OK;
-  }
-  for (int k = 0; k < nsteps; ++k) {
-    const void *src = (k & 1) ? I_b : I_a;
-    void *dst = (k & 1) ? I_a : I_b;
-    KParams pk = p;
-    const bool last = k == nsteps - 1;
-    const int nparts = total_partials(p);
-    if (diag) {
-      pk.flags |= KF_DIAG;
-      e = launch_zface(d.storage, src, c->tab_dev, p, c->inflow_dev,
-                       c->partials + (size_t)(p.nblocks + p.ngeneral) * kStepPartials, s);
-      if (e != hipSuccess) return hip_fail(e, "lbrt_step: launching the z-face flux kernel");
-    }
-    if (last && (E || F)) pk.flags |= KF_WRITE_EF;
-    e = launch(src, dst, kappa_a, kappa_s, eta, vel, c->tab_dev, pk, c->inflow_dev,
-               last ? E : nullptr, last ? F : nullptr, c->partials, s);
-    if (e != hipSuccess) return hip_fail(e, "lbrt_step: launching the step kernel");
-    if (diag) {
-      e = launch_diag_reduce(c->partials, nparts, diag, k == 0, s);
-      if (e != hipSuccess) return hip_fail(e, "lbrt_step: reducing diagnostics");
-    }
-  }
-  return LBRT_OK;
+  return run_steps(c, call, I_a, I_b, kappa_a, kappa_s, eta, vel, nsteps, E, F, diag,
+                   c->partials, c->inflow_dev, c->any_inflow_face,
+                   static_cast<hipStream_t>(stream));
 }
 
 int lbrt_adjoint_step(lbrt_ctx *c, const void *I_n, const void *lam_next, void *lam_out,
@@ -669,7 +710,7 @@ int lbrt_adjoint_step(lbrt_ctx *c, const void *I_n, const void *lam_next, void *
   const size_t bytes = storage_bytes(d.storage) * (size_t)ncell * d.ndir;
   const char *ln = static_cast<const char *>(lam_next), *lo = static_cast<const char *>(lam_out);
   if (ln < lo + bytes && lo < ln + bytes) return fail(LBRT_E_INVAL, "lam_next and lam_out overlap");
-  InflowArgs in;
+  InflowCompact in;
   bool xghosts, zghosts;
   int rc = build_inflow(c, inflow, ninflow, in, xghosts, zghosts);
   if (rc != LBRT_OK) return rc;
@@ -682,8 +723,10 @@ int lbrt_adjoint_step(lbrt_ctx *c, const void *I_n, const void *lam_next, void *
                   hipGetErrorString(e));
     }
   }
-  rc = upload_inflow(c, in, s);
-  if (rc != LBRT_OK) return rc;
+  if (c->any_inflow_face) {
+    const hipError_t e0 = launch_inflow_table(in, c->inflow_dev, s);
+    if (e0 != hipSuccess) return hip_fail(e0, "lbrt_adjoint_step: writing the inflow table");
+  }
   KParams p = make_params(c);
   hipError_t e = launch_adjoint(d.storage, I_n, lam_next, lam_out, c->adj_work, detector_face,
                                 g_kappa_a, g_kappa_s, g_eta, kappa_a, kappa_s, eta, vel,
@@ -695,12 +738,7 @@ int lbrt_adjoint_step(lbrt_ctx *c, const void *I_n, const void *lam_next, void *
 int lbrt_moments(lbrt_ctx *c, const void *I, void *E, void *F, void *stream) {
   if (!c) return fail(LBRT_E_INVAL, "ctx is NULL");
   if (!I) return fail(LBRT_E_INVAL, "I is NULL");
-  if (!E && !F) return LBRT_OK;
-  KParams p = make_params(c);
-  hipError_t e = launch_moments(c->desc.storage, I, c->tab_dev, p, E, F,
-                                static_cast<hipStream_t>(stream));
-  if (e != hipSuccess) return hip_fail(e, "lbrt_moments");
-  return LBRT_OK;
+  return moments_impl(c, I, E, F, static_cast<hipStream_t>(stream));
 }
 
 int lbrt_convert(lbrt_ctx *c, const void *src, int32_t src_storage, void *dst,

@@ -69,6 +69,18 @@ struct InflowArgs {
   const float *ghost[LBRT_MAX_DIRS][3];
 };
 
+// The same table in compact form, passed by value as a kernel argument to
+// the kernel that writes InflowArgs into device memory (a kernel node, so a
+// step with inflow planes can be captured in a graph): the call's planes,
+// and for each processing slot and axis the index of its plane or -1.
+struct InflowCompact {
+  int32_t n;
+  int32_t face[LBRT_MAX_INFLOW];
+  int32_t dir[LBRT_MAX_INFLOW];
+  const float *ptr[LBRT_MAX_INFLOW];
+  int8_t slot_plane[LBRT_MAX_DIRS][3];
+};
+
 // Waves per block of the step kernels (the wave q owns direction slots
 // [q NB / waves, (q + 1) NB / waves)).
 constexpr int waves_for(int nb) { return nb >= 112 ? 8 : 4; }
@@ -182,6 +194,8 @@ hipError_t launch_convert(const void *src, int src_storage, void *dst, int dst_s
 hipError_t launch_diag_reduce(const double *partials, int nblocks, double *diag, int first_step,
                               hipStream_t s);
 hipError_t launch_fill_f64(double *p, int n, double v, hipStream_t s);
+// Writes the ghost-plane table described by c into *out (one small block).
+hipError_t launch_inflow_table(const InflowCompact &c, InflowArgs *out, hipStream_t s);
 // Adjoint of one step (FP32 or FP64 storage): nu is a work buffer of one
 // state; gradients are added into g_ka, g_ks, g_eta.
 hipError_t launch_adjoint(int storage, const void *I, const void *lam_next, void *lam_out,

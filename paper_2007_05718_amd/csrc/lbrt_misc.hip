@@ -102,6 +102,23 @@ diag_reduce_kernel(const double *__restrict__ partials, int nblocks, double *__r
   }
 }
 
+// The ghost-plane table of a call, from its compact kernel-argument form.
+__global__ void __launch_bounds__(kBlock)
+inflow_table_kernel(const InflowCompact c, InflowArgs *__restrict__ out) {
+  const int t = threadIdx.x;
+  for (int k = t; k < LBRT_MAX_DIRS; k += kBlock)
+    for (int a = 0; a < 3; ++a) {
+      const int j = c.slot_plane[k][a];
+      out->ghost[k][a] = j >= 0 ? c.ptr[j] : nullptr;
+    }
+  if (t < LBRT_MAX_INFLOW) {
+    out->face[t] = c.face[t];
+    out->dir[t] = c.dir[t];
+    out->ptr[t] = c.ptr[t];
+  }
+  if (t == 0) out->n = c.n;
+}
+
 __global__ void fill_f64_kernel(double *p, int n, double v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -187,6 +204,11 @@ hipError_t launch_zface(int storage, const void *I, const void *tab, const KPara
                          p, inflow, partials);
       break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_inflow_table(const InflowCompact &c, InflowArgs *out, hipStream_t s) {
+  hipLaunchKernelGGL(inflow_table_kernel, dim3(1), dim3(kBlock), 0, s, c, out);
   return hipGetLastError();
 }
 

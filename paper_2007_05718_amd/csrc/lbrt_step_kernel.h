@@ -234,16 +234,11 @@ constexpr int waves_per_simd(int nb) { return sizeof(S) == 2 ? (nb >= 112 ? 2 : 
 // FP64 taps take two VGPRs each, so FP64 keeps 2 slots ahead; the 16-bit
 // forms (which need a few more VGPRs for their conversions) and the moving
 // fluid keep 3, which holds them under 128 VGPRs without spills.
-#ifdef LBRT_PF_DEPTH
-template <typename S, bool MOVING = false>
-constexpr int pf_depth(int m) { return m < LBRT_PF_DEPTH ? m : LBRT_PF_DEPTH; }
-#else
 template <typename S, bool MOVING = false>
 constexpr int pf_depth(int m) {
   const int d = sizeof(S) == 8 ? 2 : ((sizeof(S) == 2 || MOVING || m > 14) ? 3 : 4);
   return m < d ? m : d;
 }
-#endif
 
 // Fixed-order pairwise sum of W per-wave values, ((v0 + v1) + (v2 + v3)) + ...
 template <typename T, int W>

@@ -79,6 +79,23 @@ def test_adjoint_matches_oracle(storage, tol, moving, bc, planes):
     assert max(errs.values()) < tol
 
 
+@pytest.mark.parametrize("face", [wl.FACE_MY, wl.FACE_PY, wl.FACE_PZ, wl.FACE_MZ])
+def test_adjoint_detector_on_y_and_z_faces(face):
+    """Detector faces other than x on a box with non-periodic x and y: at
+    edge and corner cells part of a population's outflux is booked on an
+    earlier face (x before y before z), so the adjoint's detector weights
+    must follow that rule for the returned L and gradient to belong to one
+    objective.  FP64, against the oracle's L and gradient."""
+    p = _f64(wl.random_problem(63, shape=(7, 9, 70), npoints=26, steps=4, moving_fluid=True,
+                               vmax=0.4, bc=(wl.BC_OUTFLOW,) * 6, kappa_range=(-1.0, 1.0)))
+    got = _gpu_gradient(p, gh.lib().LBRT_FP64, steps=4, face=face, K=2)
+    L, gka, gks, geta = orc.detected_energy_gradient(p, 4, face=face, I0=got["I0_eff"])
+    errs = {k: gh.rel_l2(got[k], ref) for k, ref in (("ka", gka), ("ks", gks), ("eta", geta))}
+    print(f"face {face}: L {got['L']:.15g} vs {L:.15g}; grad rel L2 {errs}", flush=True)
+    assert abs(got["L"] - L) < 1e-12 * abs(L)
+    assert max(errs.values()) < 1e-10
+
+
 def test_adjoint_shear_flow_32():
     """The moving-fluid workload (log-normal kappa_a, relativistic shear flow,
     146 directions) at 32^3, FP32, 16 steps checkpointed every 8, gradient

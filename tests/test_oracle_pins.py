@@ -151,6 +151,26 @@ def test_outflux_corner_worked_example():
     assert influx == 0.0
 
 
+@pytest.mark.parametrize("bc", [
+    (wl.BC_OUTFLOW,) * 6,
+    (wl.BC_PERIODIC, wl.BC_PERIODIC) + (wl.BC_OUTFLOW,) * 4,
+    (wl.BC_OUTFLOW, wl.BC_INFLOW, wl.BC_OUTFLOW, wl.BC_OUTFLOW, wl.BC_PERIODIC, wl.BC_PERIODIC),
+])
+def test_detector_weights_give_the_face_outflux(bc):
+    """The adjoint's detector weights d (one linear functional per face)
+    reproduce the face entries of boundary_fluxes, which evaluates the pull
+    at destinations outside the box: sum d * I equals the booked outflux on
+    every face, including edge and corner cells (first of x, y, z)."""
+    p = _problem(shape=(5, 6, 7), npoints=26, dt=0.7, bc=bc)
+    out, _ = orc.boundary_fluxes(p.I0, p)
+    for face in range(6):
+        d = orc.detector_weights(p, face)
+        got = float(np.sum(d * p.I0))
+        assert abs(got - out[face]) < 1e-14 * p.I0.sum(), (face, got, out[face])
+        if bc[face] == wl.BC_PERIODIC:
+            assert not d.any()
+
+
 def test_inflow_ghost_enters_by_its_weight():
     """Sec. 4.1.1 beam injection: a unit ghost value on face -x for direction
     +x reaches the first layer with weight dt |n^x| / dx and nothing else."""
