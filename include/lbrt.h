@@ -165,12 +165,33 @@ void lbrt_destroy(lbrt_ctx *ctx);
  * kernel from the call's arguments), so it can be captured in a HIP graph,
  * except for a call with diag that first grows the context's partials
  * buffer (one hipMalloc when the tiling needs more rows than lbrt_init
- * sized).
+ * sized; lbrt_step_noalloc never allocates).
  */
 int lbrt_step(lbrt_ctx *ctx, void *I_a, void *I_b,
               const float *kappa_a, const float *kappa_s, const float *eta,
               const float *vel, const lbrt_inflow *inflow, int32_t ninflow,
               int32_t nsteps, void *E, void *F, double *diag, void *stream);
+
+/*
+ * lbrt_step without allocation, for callers that cannot call hipMalloc:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  Arguments, results and errors are those of lbrt_step (the
+ * same kernels, bit-identical results).  The work memory (the ghost-plane
+ * table and the per-block diagnostic partials) is a fixed 4 MiB array in
+ * device memory, one per GPU, held until the process ends; the call
+ * allocates nothing and copies nothing from the host (the ghost table is
+ * written by a kernel from its arguments).  With diag != NULL the call
+ * needs one 72-byte partial row per step-kernel block plus the z-face
+ * blocks; more than the array holds (about 58,000 rows: 256^3 with the
+ * default tiling needs about 13,000) is rejected with LBRT_E_INVAL before
+ * any launch.  The context's device must be the current device.
+ * Every call on one GPU uses that GPU's array: calls that can overlap on
+ * one GPU (different streams, or host threads, without ordering) race.
+ */
+int lbrt_step_noalloc(lbrt_ctx *ctx, void *I_a, void *I_b,
+                      const float *kappa_a, const float *kappa_s, const float *eta,
+                      const float *vel, const lbrt_inflow *inflow, int32_t ninflow,
+                      int32_t nsteps, void *E, void *F, double *diag, void *stream);
 
 /*
  * Adjoint of one step, for the reverse sweep of a run whose objective is

@@ -84,6 +84,8 @@ def _load():
     lib.lbrt_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(lbrt_inflow), i32,
                               i32, vp, vp, vp, vp]
     lib.lbrt_step.restype = ctypes.c_int
+    lib.lbrt_step_noalloc.argtypes = lib.lbrt_step.argtypes
+    lib.lbrt_step_noalloc.restype = ctypes.c_int
     lib.lbrt_moments.argtypes = [vp, vp, vp, vp, vp]
     lib.lbrt_moments.restype = ctypes.c_int
     lib.lbrt_convert.argtypes = [vp, vp, i32, vp, i32, vp]
@@ -284,6 +286,25 @@ def lbrt_step(ctx: Context, I_a, I_b, kappa_a, kappa_s, eta, vel=None, inflow=No
     _check(rc)
 
 
+def lbrt_step_noalloc(ctx: Context, I_a, I_b, kappa_a, kappa_s, eta, vel=None, inflow=None,
+                      nsteps: int = 1, E=None, F=None, diag=None, stream=None) -> None:
+    """``lbrt_step`` through the entry point that allocates nothing (its work
+    memory is the library's fixed per-GPU scratch); same arguments."""
+    d = ctx.desc
+    n, nc = d.ndir, d.ncell
+    st = d.c.storage
+    planes, nin = _inflow_planes(d, inflow)
+    f32 = _torch().float32
+    rc = _lib.lbrt_step_noalloc(
+        ctx.handle, _ptr(I_a, "I_a", n * nc, _pop_dtype(st)),
+        _ptr(I_b, "I_b", n * nc, _pop_dtype(st)),
+        _ptr(kappa_a, "kappa_a", nc, f32), _ptr(kappa_s, "kappa_s", nc, f32),
+        _ptr(eta, "eta", nc, f32), _ptr(vel, "vel", 3 * nc, f32), planes, nin, int(nsteps),
+        _ptr(E, "E", nc, _moment_dtype(st)), _ptr(F, "F", 3 * nc, _moment_dtype(st)),
+        _ptr(diag, "diag", LBRT_DIAG_LEN, _torch().float64), _stream(stream))
+    _check(rc)
+
+
 def lbrt_adjoint_step(ctx: Context, I_n, lam_next, lam_out, detector_face: int, g_kappa_a,
                       g_kappa_s, g_eta, kappa_a, kappa_s, eta, vel=None, inflow=None,
                       stream=None) -> None:
@@ -391,7 +412,8 @@ def lbrt_batch_destroy(batch: Batch) -> None:
 
 def exported_symbols() -> list:
     """Names of the C entry points the binding wraps."""
-    return ["lbrt_validate", "lbrt_init", "lbrt_destroy", "lbrt_step", "lbrt_moments",
+    return ["lbrt_validate", "lbrt_init", "lbrt_destroy", "lbrt_step", "lbrt_step_noalloc",
+            "lbrt_moments",
             "lbrt_convert", "lbrt_adjoint_step", "lbrt_set_tiling", "lbrt_get_tiling",
             "lbrt_batch_create", "lbrt_step_batched", "lbrt_batch_destroy", "lbrt_last_error"]
 

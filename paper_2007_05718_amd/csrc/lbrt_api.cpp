@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -43,6 +44,21 @@ size_t storage_bytes(int s) {
 
 struct TileShape { int tx, ty; };
 
+// Device memory of lbrt_step_noalloc, for callers that cannot allocate: the
+// ghost-plane table, then the per-block diagnostic partials.  One copy per
+// GPU for the life of the process; every call on that GPU reuses it.
+constexpr size_t kScratchBytes = (size_t)4 << 20;
+constexpr size_t kScratchTableBytes = (sizeof(InflowArgs) + 255) / 256 * 256;
+constexpr int kScratchMaxPartials =
+    (int)((kScratchBytes - kScratchTableBytes) / (sizeof(double) * kStepPartials));
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// scratch's device address on each GPU (hipGetSymbolAddress with that GPU
+// current); host code passes these, never the array's name.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
 }  // namespace
 
 struct lbrt_ctx {
@@ -72,6 +88,7 @@ struct lbrt_ctx {
   int ngeneral[2] = {0, 0};
   int main_zr0[2] = {0, 0}, main_nzr[2] = {0, 0};
   int device = 0;
+  unsigned char *scratch = nullptr;  // this device's scratch (lbrt_step_noalloc)
 };
 
 namespace {
@@ -601,6 +618,26 @@ int lbrt_init(const lbrt_desc *d, lbrt_ctx **out) {
     if (v > 0) c->zlen_general = v;
   }
   (void)hipGetDevice(&c->device);
+  if (c->device < 0 || c->device >= kMaxDevices) {
+    rc = fail(LBRT_E_UNSUPPORTED, "device %d: at most %d devices", c->device, kMaxDevices);
+    delete c;
+    return rc;
+  }
+  {
+    // once per device, with that device current
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[c->device]) {
+      void *ptr = nullptr;
+      const hipError_t es = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (es != hipSuccess || !ptr) {
+        rc = fail(LBRT_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(es));
+        delete c;
+        return rc;
+      }
+      g_scratch_ptr[c->device] = ptr;
+    }
+    c->scratch = static_cast<unsigned char *>(g_scratch_ptr[c->device]);
+  }
 
   hipError_t e;
   size_t tab_bytes;
@@ -686,6 +723,31 @@ int lbrt_step(lbrt_ctx *c, void *I_a, void *I_b, const float *kappa_a, const flo
   return run_steps(c, call, I_a, I_b, kappa_a, kappa_s, eta, vel, nsteps, E, F, diag,
                    c->partials, c->inflow_dev, c->any_inflow_face,
                    static_cast<hipStream_t>(stream));
+}
+
+int lbrt_step_noalloc(lbrt_ctx *c, void *I_a, void *I_b, const float *kappa_a,
+                      const float *kappa_s, const float *eta, const float *vel,
+                      const lbrt_inflow *inflow, int32_t ninflow, int32_t nsteps, void *E,
+                      void *F, double *diag, void *stream) {
+  StepCall call;
+  int rc = prepare_step(c, I_a, I_b, kappa_a, kappa_s, eta, vel, inflow, ninflow, nsteps, call);
+  if (rc != LBRT_OK) return rc;
+  if (!c->scratch) return fail(LBRT_E_HIP, "lbrt_step_noalloc: no scratch on device %d", c->device);
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != c->device)
+    return fail(LBRT_E_INVAL, "lbrt_step_noalloc: the context's device %d is not current (%d)",
+                c->device, cur);
+  const int need = total_partials(call.p);
+  if (diag && need > kScratchMaxPartials)
+    return fail(LBRT_E_INVAL,
+                "lbrt_step_noalloc: diagnostics need %d block partials (%zu bytes), more than "
+                "the %d (%zu bytes) of the fixed scratch; use lbrt_step or pass diag = NULL",
+                need, (size_t)need * sizeof(double) * kStepPartials, kScratchMaxPartials,
+                kScratchBytes - kScratchTableBytes);
+  InflowArgs *table = reinterpret_cast<InflowArgs *>(c->scratch);
+  double *partials = reinterpret_cast<double *>(c->scratch + kScratchTableBytes);
+  return run_steps(c, call, I_a, I_b, kappa_a, kappa_s, eta, vel, nsteps, E, F, diag, partials,
+                   table, true, static_cast<hipStream_t>(stream));
 }
 
 int lbrt_adjoint_step(lbrt_ctx *c, const void *I_n, const void *lam_next, void *lam_out,
