@@ -4,20 +4,28 @@ A step is one fused stream-and-collide pass (trilinear pull with inflow and
 vacuum faces, per-cell moments, implicit collision, store of the new
 populations, E and F, and the FP64 boundary/energy diagnostics) over the
 crossing-beams-plus-shadow workload: 256^3 cells, the 110-direction
-degree-17 Lebedev rule, FP32 population storage.  The same workload is
-then timed with BF16 and FP16 population storage.
+degree-17 Lebedev rule, FP32 population storage.
 
 Prints ONE JSON line.  `value` is cell-direction updates per second (GDUPS)
 of the FP32 form with all inputs resident in HBM.  The roofline entry is
 for the fused step (its main and boundary kernels, one lbrt_step call
 without diagnostics): algorithmic bytes per call over the call's mean
-duration, timed with HIP events on the stream the kernels run on.
-Further forms on the same GPU: BF16 and FP16 storage of the same workload,
-the batched sweep of 512 uneven domains (one multi-domain launch per step,
-against the same domains run one by one), and the moving-fluid run with its
-adjoint (forward steps and the checkpointed reverse sweep).
+duration, timed with HIP events on the stream the kernels run on; beside it
+the rate of a hand-written streaming copy on the same GPU.
+Further forms on the same GPU:
+* BF16 and FP16 storage of the same workload, each with its error against
+  the FP64 oracle over the full 500-step run of the workload scaled to 64^3
+  (the oracle's moments are the committed tests/golden/beams64_500.npz);
+* the collision kinds (explicit, Lambda iteration with 5 cycles, implicit)
+  on the beams geometry with capped opacities, where the explicit step is
+  stable (the cost comparison of the paper's Sec. 6);
+* the batched sweep of 512 uneven domains (two multi-domain launches per
+  step), eager and as a replayed graph, against the same domains run one by
+  one;
+* the moving-fluid run with its adjoint (forward steps and the checkpointed
+  reverse sweep).
 The CPU baseline is the FP64 oracle (test infrastructure) timed on a bounded
-sample of the same workload on this host.
+sample of the same workload on this host, on one core and on all cores.
 """
 from __future__ import annotations
 
@@ -143,22 +151,103 @@ def kernel_only_ms(L, torch, prob, storage, steps):
     return float(np.mean(ms))
 
 
-def copy_ceiling_gbs(torch, nbytes: int = 4 << 30, reps: int = 10) -> float:
-    """Read+write bandwidth of a plain device-to-device copy (torch's copy kernel)."""
+def copy_ceiling_gbs(L, torch, nbytes: int = 4 << 30, reps: int = 10) -> dict:
+    """Read+write bandwidth of a plain device-to-device copy: the library's
+    hand-written streaming copy (16-byte loads, non-temporal stores) and
+    torch's copy kernel, same buffers."""
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     a.fill_(1.0)
-    b.copy_(a)
-    torch.cuda.synchronize()
-    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    s.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e.record()
-    torch.cuda.synchronize()
-    ms = s.elapsed_time(e) / reps
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, fn in (("stream_copy", lambda: L.lbrt_stream_copy(a, b, stream=stream.cuda_stream)),
+                     ("torch_copy", lambda: b.copy_(a))):
+        fn()
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record(stream)
+        for _ in range(reps):
+            fn()
+        e.record(stream)
+        torch.cuda.synchronize()
+        ms = s.elapsed_time(e) / reps
+        out[name] = round(2 * nbytes / (ms * 1e-3) / 1e9, 1)
     del a, b
-    return 2 * nbytes / (ms * 1e-3) / 1e9
+    return out
+
+
+def form_error(L, torch, storage) -> dict:
+    """Error of a storage form against the FP64 oracle over the full run of
+    the beams workload scaled to 64^3 (500 steps from zero): relative L2 and
+    max |d| / max |ref| of E and of F."""
+    import workloads as wl
+    path = os.path.join(ROOT, "tests", "golden", "beams64_500.npz")
+    ref = np.load(path)
+    prob = wl.beams(n=int(ref["n"]), steps=int(ref["steps"]), alloc_state=False)
+    ctx = L.lbrt_init(L.Desc.from_problem(prob, storage=storage))
+    dt = {L.LBRT_FP32: torch.float32, L.LBRT_BF16: torch.bfloat16,
+          L.LBRT_FP16: torch.float16}[storage]
+    n = prob.ndir * prob.ncell
+    Ia = torch.zeros(n, dtype=dt, device="cuda")
+    Ib = torch.zeros(n, dtype=dt, device="cuda")
+    f = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).reshape(-1).cuda()
+    inflow = [(p.face, p.direction, f(p.values)) for p in prob.inflow]
+    E = torch.empty(prob.ncell, device="cuda")
+    F = torch.empty(3 * prob.ncell, device="cuda")
+    L.lbrt_step(ctx, Ia, Ib, f(prob.kappa_a), f(prob.kappa_s), f(prob.eta), inflow=inflow,
+                nsteps=prob.steps, E=E, F=F)
+    torch.cuda.synchronize()
+    e = E.double().cpu().numpy().reshape(prob.shape)
+    fl = F.double().cpu().numpy().reshape((3,) + prob.shape)
+    ctx.close()
+    Er, Fr = ref["E"], ref["F"]
+    l2 = lambda a, b: float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+    return {"workload": f"beams {prob.nx}^3 x {prob.ndir}, {prob.steps} steps, vs FP64 oracle",
+            "E_rel_l2": float(f"{l2(e, Er):.3e}"), "F_rel_l2": float(f"{l2(fl, Fr):.3e}"),
+            "E_max_rel": float(f"{np.max(np.abs(e - Er)) / np.max(np.abs(Er)):.3e}"),
+            "F_max_rel": float(f"{np.max(np.abs(fl - Fr)) / np.max(np.abs(Fr)):.3e}")}
+
+
+def time_collisions(L, torch, n: int, steps: int, warmup: int) -> dict:
+    """ms per step of the three collision kinds (FP32, no outputs) on the
+    beams geometry with capped opacities, and each one's ratio to the
+    implicit (closed-form) step."""
+    import workloads as wl
+    prob = wl.beams_costs(n=n, alloc_state=False)
+    out = {"workload": f"beams geometry {n}^3 x {prob.ndir}, kappa_a <= 1, kappa_s = 0.5, "
+                       "FP32, no outputs"}
+    kinds = (("implicit", L.LBRT_COLL_IMPLICIT, 1), ("explicit", L.LBRT_COLL_EXPLICIT, 1),
+             ("lambda5", L.LBRT_COLL_LAMBDA, 5))
+    f = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).reshape(-1).cuda()
+    ka, ks, eta = f(prob.kappa_a), f(prob.kappa_s), f(prob.eta)
+    inflow = [(p.face, p.direction, f(p.values)) for p in prob.inflow]
+    nn = prob.ndir * prob.ncell
+    Ia = torch.zeros(nn, device="cuda")
+    Ib = torch.zeros(nn, device="cuda")
+    stream = torch.cuda.current_stream()
+    for name, coll, iters in kinds:
+        ctx = L.lbrt_init(L.Desc.from_problem(prob, collision=coll, lambda_iters=iters))
+        bufs = [Ia, Ib]
+        for k in range(warmup):
+            L.lbrt_step(ctx, bufs[k % 2], bufs[(k + 1) % 2], ka, ks, eta, inflow=inflow,
+                        stream=stream.cuda_stream)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
+        for k in range(steps):
+            evs[k][0].record(stream)
+            L.lbrt_step(ctx, bufs[k % 2], bufs[(k + 1) % 2], ka, ks, eta, inflow=inflow,
+                        stream=stream.cuda_stream)
+            evs[k][1].record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+        out[name] = {"ms_per_step": round(ms, 4),
+                     "GDUPS": round(prob.ndir * prob.ncell / (ms * 1e-3) / 1e9, 2)}
+        ctx.close()
+    for name, _, _ in kinds:
+        out[name]["ratio_to_implicit"] = round(out[name]["ms_per_step"]
+                                               / out["implicit"]["ms_per_step"], 3)
+    del Ia, Ib
+    return out
 
 
 def time_batched(L, torch, ndomains=512, seed=4, sequential=True):
@@ -189,10 +278,26 @@ def time_batched(L, torch, ndomains=512, seed=4, sequential=True):
     e1.record(stream)
     torch.cuda.synchronize()
     t_batch = e0.elapsed_time(e1) * 1e-3
+    # the same sweep captured once in a graph and replayed
+    gs = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=gs):
+        L.lbrt_step_batched(b, stream=gs.cuda_stream)
+    g.replay()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_graph = e0.elapsed_time(e1) * 1e-3
     out = {"domains": ndomains, "updates": updates,
            "GDUPS": round(updates / t_batch / 1e9, 2), "seconds": round(t_batch, 3),
+           "graph_GDUPS": round(updates / t_graph / 1e9, 2), "graph_seconds": round(t_graph, 3),
+           "launches": 2 * max(p.steps for p in probs),
            "hbm_GBs_algorithmic": round(updates * algorithmic_bytes_per_cell(50, 4) / 50
                                         / t_batch / 1e9, 1)}
+    del g
     if sequential:
         e0.record(stream)
         for dm in doms:
@@ -241,30 +346,55 @@ def time_adjoint(L, torch, n=192, steps=64, K=8):
     return out
 
 
-def cpu_baseline(prob, planes: int = 16):
-    """FP64 oracle, one step on a slab of `planes` z-planes of the workload."""
+def _oracle_slab_step(args):
+    """One FP64 oracle step on z-planes [z0, z0 + planes) of the workload
+    (a slab with vacuum cut faces); returns (updates, seconds)."""
+    n, z0, planes, seed = args
     import copy
 
     import workloads as wl
     from oracle import lbrt_oracle as orc
+    prob = wl.beams(n=n, alloc_state=False)
     q = copy.copy(prob)
     q.nz = planes
-    q.kappa_a = prob.kappa_a[:planes]
-    q.kappa_s = prob.kappa_s[:planes]
-    q.eta = prob.eta[:planes]
+    q.kappa_a = prob.kappa_a[z0:z0 + planes]
+    q.kappa_s = prob.kappa_s[z0:z0 + planes]
+    q.eta = prob.eta[z0:z0 + planes]
     q.inflow = [wl.InflowPlane(p.face, p.direction,
-                               p.values[:planes] if p.face in (0, 1, 2, 3) else p.values)
+                               p.values[z0:z0 + planes] if p.face in (0, 1, 2, 3) else p.values)
                 for p in prob.inflow]
-    rng = np.random.default_rng(0)
+    rng = np.random.default_rng(seed)
     I = rng.uniform(0.0, 1.0, (q.ndir, planes, q.ny, q.nx)) * q.weights[:, None, None, None]
     t0 = time.perf_counter()
     orc.step(I, q)
-    sec = time.perf_counter() - t0
-    updates = q.ndir * q.ncell
-    return {"value": updates / sec / 1e9, "unit": "GDUPS", "cores": 1, "kind": "oracle",
-            "sample": f"one FP64 step on a {q.nx}x{q.ny}x{planes} slab of the workload "
-                      f"({q.ndir} directions, {updates:.3g} updates, {sec:.1f} s, numpy, "
-                      f"single thread)"}
+    return q.ndir * q.ncell, time.perf_counter() - t0
+
+
+def cpu_baseline(n: int, planes: int = 8, workers: int = 0) -> dict:
+    """The FP64 oracle on this host: one step on slabs of `planes` z-planes of
+    the workload, first on one core (two slabs in turn), then on all cores
+    (one slab per worker process, in parallel).  Runs before the GPU is
+    touched, so the worker processes start from a clean parent."""
+    import multiprocessing as mp
+    ncpu = os.cpu_count() or 1
+    workers = workers or min(ncpu, 16)
+    one = [_oracle_slab_step((n, 8 * k, planes, k)) for k in range(2)]
+    upd1 = sum(u for u, _ in one)
+    sec1 = sum(t for _, t in one)
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        pool.map(abs, range(workers))       # start the workers
+        t0 = time.perf_counter()
+        res = pool.map(_oracle_slab_step,
+                       [(n, (planes * k) % (n - planes), planes, 100 + k) for k in range(workers)])
+        wall = time.perf_counter() - t0
+    updn = sum(u for u, _ in res)
+    return {"value": updn / wall / 1e9, "unit": "GDUPS", "cores": workers, "kind": "oracle",
+            "single_core_GDUPS": upd1 / sec1 / 1e9, "host_cpus": ncpu,
+            "sample": f"FP64 oracle (numpy), one step on {n}x{n}x{planes} slabs of the workload "
+                      f"({planes * n * n * 110:.3g} updates each): 2 slabs on 1 core "
+                      f"({sec1:.1f} s), then {workers} slabs on {workers} worker processes in "
+                      f"parallel ({wall:.1f} s wall); host has {ncpu} CPUs"}
 
 
 def traffic_entry(ndir, ncell):
@@ -291,8 +421,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=256, help="grid edge (default 256)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
-    ap.add_argument("--forms", default="bf16,fp16,batched,adjoint",
-                    help="extra forms to time (bf16, fp16, batched, adjoint)")
+    ap.add_argument("--forms", default="bf16,fp16,collisions,batched,adjoint",
+                    help="extra forms to time (bf16, fp16, collisions, batched, adjoint)")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batched form: skip the one-domain-at-a-time comparison")
     args = ap.parse_args()
@@ -300,6 +430,11 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU slab decomposition is a design, not built).", file=sys.stderr)
         sys.exit(2)
+
+    cpu = None
+    if not args.no_cpu:
+        log("timing the oracle on the host (before the GPU is used)")
+        cpu = cpu_baseline(args.n)
 
     import torch
     import paper_2007_05718_amd as L
@@ -319,7 +454,11 @@ def main():
     bytes_launch = bpc * ncell
     achieved = bytes_launch / (kms * 1e-3) / 1e9
     forms = {}
-    for name in [s for s in args.forms.split(",") if s]:
+    names = [s for s in args.forms.split(",") if s]
+    if any(n in ("bf16", "fp16") for n in names):
+        log("fp32 error against the oracle (64^3, 500 steps)")
+        forms["fp32_error_vs_oracle"] = form_error(L, torch, L.LBRT_FP32)
+    for name in names:
         if name in ("bf16", "fp16"):
             st = {"bf16": L.LBRT_BF16, "fp16": L.LBRT_FP16}[name]
             log(f"timing {name}")
@@ -332,7 +471,11 @@ def main():
                 "kernel_ms": round(k2, 4),
                 "hbm_GBs_algorithmic": round(b2 / (k2 * 1e-3) / 1e9, 1),
                 "speedup_vs_fp32": round(wall / w2, 3),
+                "error_vs_oracle": form_error(L, torch, st),
             }
+        elif name == "collisions":
+            log("timing the collision kinds")
+            forms["collision_costs"] = time_collisions(L, torch, args.n, args.steps, args.warmup)
         elif name == "batched":
             log("timing the batched sweep (512 domains)")
             try:
@@ -348,11 +491,7 @@ def main():
                 forms["moving_adjoint_192"] = {"error": repr(exc)}
         torch.cuda.empty_cache()
     log("copy ceiling")
-    copy_gbs = copy_ceiling_gbs(torch)
-    cpu = None
-    if not args.no_cpu:
-        log("timing the oracle on the host")
-        cpu = cpu_baseline(prob)
+    copy_gbs = copy_ceiling_gbs(L, torch)
     tr = traffic_entry(ndir, ncell)
     out = {
         "metric": METRIC,
@@ -385,7 +524,9 @@ def main():
             "kernel": "step_kernel_main<float,112> + step_kernel_general<float,112>",
             "kernel_ms": round(kms, 4),
             "bytes_per_launch_algorithmic": bytes_launch,
-            "copy_kernel_GBs": round(copy_gbs, 1),
+            "copy_kernel_GBs": copy_gbs["stream_copy"],
+            "torch_copy_GBs": copy_gbs["torch_copy"],
+            "frac_of_copy": round(achieved / copy_gbs["stream_copy"], 4),
         },
         "cpu_baseline": cpu,
         "forms": forms,

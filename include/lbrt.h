@@ -275,6 +275,12 @@ int lbrt_batch_create(const lbrt_domain *domains, int32_t ndomains, lbrt_batch *
 int lbrt_step_batched(lbrt_batch *batch, void *stream);
 void lbrt_batch_destroy(lbrt_batch *batch);
 
+/* A plain streaming copy of `bytes` (a multiple of 16; 16-byte aligned,
+ * non-overlapping device buffers): 16-byte loads and non-temporal stores.
+ * Not part of the method: the measured read-plus-write bandwidth ceiling
+ * that the step kernels are compared with. */
+int lbrt_stream_copy(const void *src, void *dst, int64_t bytes, void *stream);
+
 /* Message describing the last error returned on the calling thread
  * (empty string if none).  The pointer stays valid until the thread's next
  * lbrt call. */

@@ -104,6 +104,8 @@ def _load():
     lib.lbrt_step_batched.restype = ctypes.c_int
     lib.lbrt_batch_destroy.argtypes = [vp]
     lib.lbrt_batch_destroy.restype = None
+    lib.lbrt_stream_copy.argtypes = [vp, vp, ctypes.c_int64, vp]
+    lib.lbrt_stream_copy.restype = ctypes.c_int
     lib.lbrt_last_error.argtypes = []
     lib.lbrt_last_error.restype = ctypes.c_char_p
     return lib
@@ -410,12 +412,23 @@ def lbrt_batch_destroy(batch: Batch) -> None:
     batch.close()
 
 
+def lbrt_stream_copy(src, dst, stream=None) -> None:
+    """Streaming copy of a device tensor into another of the same size (the
+    bandwidth ceiling of the measurements)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst differ in size")
+    _check(_lib.lbrt_stream_copy(_ptr(src, "src"), _ptr(dst, "dst"), int(nbytes),
+                                 _stream(stream)))
+
+
 def exported_symbols() -> list:
     """Names of the C entry points the binding wraps."""
     return ["lbrt_validate", "lbrt_init", "lbrt_destroy", "lbrt_step", "lbrt_step_noalloc",
             "lbrt_moments",
             "lbrt_convert", "lbrt_adjoint_step", "lbrt_set_tiling", "lbrt_get_tiling",
-            "lbrt_batch_create", "lbrt_step_batched", "lbrt_batch_destroy", "lbrt_last_error"]
+            "lbrt_batch_create", "lbrt_step_batched", "lbrt_batch_destroy", "lbrt_stream_copy",
+            "lbrt_last_error"]
 
 
 def library():

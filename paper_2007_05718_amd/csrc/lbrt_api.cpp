@@ -823,6 +823,20 @@ int lbrt_convert(lbrt_ctx *c, const void *src, int32_t src_storage, void *dst,
   return LBRT_OK;
 }
 
+int lbrt_stream_copy(const void *src, void *dst, int64_t bytes, void *stream) {
+  if (!src || !dst) return fail(LBRT_E_INVAL, "src and dst are required");
+  if (bytes < 0 || bytes % 16 != 0) return fail(LBRT_E_INVAL, "bytes = %lld: need a multiple of 16",
+                                                (long long)bytes);
+  if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) % 16 != 0)
+    return fail(LBRT_E_INVAL, "src and dst must be 16-byte aligned");
+  const char *a = static_cast<const char *>(src), *b = static_cast<const char *>(dst);
+  if (a < b + bytes && b < a + bytes) return fail(LBRT_E_INVAL, "src and dst overlap");
+  if (bytes == 0) return LBRT_OK;
+  hipError_t e = launch_stream_copy(src, dst, bytes / 16, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "lbrt_stream_copy");
+  return LBRT_OK;
+}
+
 }  // extern "C"
 
 struct lbrt_batch {

@@ -194,6 +194,8 @@ hipError_t launch_convert(const void *src, int src_storage, void *dst, int dst_s
 hipError_t launch_diag_reduce(const double *partials, int nblocks, double *diag, int first_step,
                               hipStream_t s);
 hipError_t launch_fill_f64(double *p, int n, double v, hipStream_t s);
+// Streaming copy of n16 16-byte elements (the measured bandwidth ceiling).
+hipError_t launch_stream_copy(const void *src, void *dst, int64_t n16, hipStream_t s);
 // Writes the ghost-plane table described by c into *out (one small block).
 hipError_t launch_inflow_table(const InflowCompact &c, InflowArgs *out, hipStream_t s);
 // Adjoint of one step (FP32 or FP64 storage): nu is a work buffer of one

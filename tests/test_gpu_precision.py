@@ -1,0 +1,50 @@
+"""The precision form on the crossing-beams-plus-shadow workload over its full
+run: 500 steps from zero, the 110-direction rule, scaled to 64^3 cells, in
+FP32, BF16 and FP16 population storage, against the FP64 oracle's moments
+(tests/golden/beams64_500.npz, written by make_beams_golden.py, which calls
+only the oracle).
+
+Errors are reported for E and for F as global relative L2 and as
+max |got - ref| / max |ref|.  FP32 storage: 1e-5, both ways.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+import gpu_helpers as gh  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "beams64_500.npz")
+
+
+def _errors(E, F, ref):
+    Er, Fr = ref["E"], ref["F"]
+    out = {
+        "E_rel_l2": gh.rel_l2(E, Er),
+        "F_rel_l2": gh.rel_l2(F, Fr),
+        "E_max_rel": float(np.max(np.abs(E - Er)) / np.max(np.abs(Er))),
+        "F_max_rel": float(max(np.max(np.abs(F[a] - Fr[a])) for a in range(3))
+                           / np.max(np.abs(Fr))),
+    }
+    return out
+
+
+@pytest.mark.parametrize("storage,tol_l2,tol_max", [
+    ("fp32", 1e-5, 1e-5),
+])
+def test_beams64_500_steps_against_oracle(storage, tol_l2, tol_max):
+    L = gh.lib()
+    st = {"fp32": L.LBRT_FP32, "fp16": L.LBRT_FP16, "bf16": L.LBRT_BF16}[storage]
+    ref = np.load(GOLDEN)
+    prob = wl.beams(n=int(ref["n"]), steps=int(ref["steps"]))
+    print(prob.name, prob.shape, prob.ndir, prob.steps, storage, flush=True)
+    res = gh.run_problem(prob, storage=st)
+    err = _errors(res["E"], res["F"], ref)
+    print(storage, {k: f"{v:.3e}" for k, v in err.items()}, flush=True)
+    assert err["E_rel_l2"] < tol_l2 and err["F_rel_l2"] < tol_l2
+    if tol_max is not None:
+        assert err["E_max_rel"] < tol_max and err["F_max_rel"] < tol_max

@@ -220,6 +220,23 @@ def beams(n: int = 256, npoints: int = 110, dt: float = 0.5, steps: int = 500,
     )
 
 
+def beams_costs(n: int = 256, npoints: int = 110, dt: float = 0.5, steps: int = 20,
+                seed: int = 3, kappa_s: float = 0.5, kappa_a_max: float = 1.0,
+                alloc_state: bool = True) -> Problem:
+    """The crossing-beams geometry for comparing the cost of the collision
+    kinds (Sec. 6 compares the explicit and the iterated implicit stepper):
+    the same beams and obstacle, with absorption capped at ``kappa_a_max``
+    and uniform scattering ``kappa_s`` so that the explicit step is stable
+    (dt (kappa_a + kappa_s) < 1), and emission eta = kappa_a / 10."""
+    p = beams(n=n, npoints=npoints, dt=dt, steps=steps, seed=seed, alloc_state=alloc_state)
+    ka = np.minimum(p.kappa_a, np.float32(kappa_a_max)).astype(np.float32)
+    p.kappa_a = ka
+    p.kappa_s = np.full(p.shape, kappa_s, dtype=np.float32)
+    p.eta = (ka * np.float32(0.1)).astype(np.float32)
+    p.name = f"beams_costs{n}"
+    return p
+
+
 # ---------------------------------------------------------------------------
 # Batched opacity sweep: many independent domains.
 # ---------------------------------------------------------------------------
