@@ -62,6 +62,12 @@ typedef enum {
 
 typedef enum { LBRT_BC_OUTFLOW = 0, LBRT_BC_PERIODIC = 1, LBRT_BC_INFLOW = 2 } lbrt_bc;
 typedef enum { LBRT_FP32 = 0, LBRT_FP64 = 1, LBRT_BF16 = 2, LBRT_FP16 = 3 } lbrt_storage;
+/* Rounding of populations stored as BF16/FP16 (ignored for FP32/FP64). */
+typedef enum {
+  LBRT_ROUND_STOCHASTIC = 0, /* round up with the probability of the dropped
+                                fraction: exact in expectation              */
+  LBRT_ROUND_NEAREST = 1     /* round to nearest even                         */
+} lbrt_rounding;
 typedef enum {
   LBRT_COLL_IMPLICIT = 0,   /* eq. (rte_implicit), solved exactly                */
   LBRT_COLL_EXPLICIT = 1,   /* eq. (collision-step)                              */
@@ -87,7 +93,16 @@ enum { LBRT_FACE_MX = 0, LBRT_FACE_PX = 1, LBRT_FACE_MY = 2, LBRT_FACE_PY = 3,
  *   lambda_iters  cycles for LBRT_COLL_LAMBDA (>= 1);
  *   lambda_aniso  lambda = 3 kappa_1 / kappa_0 (0 for isotropic scattering);
  *   moving_fluid  nonzero: lbrt_step takes a velocity field and uses the
- *            mixed-frame collision of App. B (implicit, lambda must be 0).
+ *            mixed-frame collision of App. B (implicit, lambda must be 0);
+ *   rounding BF16/FP16 storage: LBRT_ROUND_STOCHASTIC (0, the default) or
+ *            LBRT_ROUND_NEAREST.  Round-to-nearest loses every per-step
+ *            change below half a unit in the last place (2^-9 relative for
+ *            BF16, 2^-12 for FP16), so a weakly absorbing cell never dims a
+ *            beam; stochastic rounding is unbiased.  Its random bits per
+ *            element are a hash of the cell index and a per-step seed (drawn
+ *            from the context's count of steps taken), combined with a
+ *            constant of the direction, so a run on a fresh context is
+ *            reproducible (a captured graph replays the seeds it captured).
  * The context copies everything it needs; the caller's arrays may be freed
  * after lbrt_init returns.
  */
@@ -104,6 +119,7 @@ typedef struct {
   int32_t lambda_iters;
   double lambda_aniso;
   int32_t moving_fluid;
+  int32_t rounding;
 } lbrt_desc;
 
 /*
@@ -135,7 +151,9 @@ int lbrt_validate(const lbrt_desc *desc);
  * LBRT_TILE ("TXxTY", tx * ty = 64) and LBRT_ZLEN, LBRT_ZLEN_GENERAL (z-range
  * lengths) set the initial tiling (see lbrt_set_tiling); LBRT_FP64_FLUX_TERM
  * (any value) keeps the FP64 reference term of the per-cell flux sums where
- * it is exactly zero (rules whose antipodal pairs share a wave). */
+ * it is exactly zero (rules whose antipodal pairs share a wave); LBRT_PAIR=0
+ * runs the interior on the one-cell-per-lane kernel instead of the
+ * two-cells-per-lane one. */
 int lbrt_init(const lbrt_desc *desc, lbrt_ctx **out);
 
 /* Free the context's device tables.  NULL is accepted. */

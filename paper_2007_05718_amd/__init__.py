@@ -25,6 +25,7 @@ LBRT_E_NOMEM, LBRT_E_HIP, LBRT_E_UNSUPPORTED = -4, -5, -6
 LBRT_BC_OUTFLOW, LBRT_BC_PERIODIC, LBRT_BC_INFLOW = 0, 1, 2
 LBRT_FP32, LBRT_FP64, LBRT_BF16, LBRT_FP16 = 0, 1, 2, 3
 LBRT_COLL_IMPLICIT, LBRT_COLL_EXPLICIT, LBRT_COLL_LAMBDA = 0, 1, 2
+LBRT_ROUND_STOCHASTIC, LBRT_ROUND_NEAREST = 0, 1
 LBRT_MAX_DIRS, LBRT_MAX_INFLOW, LBRT_DIAG_LEN = 152, 32, 9
 
 STORAGE_BYTES = {LBRT_FP32: 4, LBRT_FP64: 8, LBRT_BF16: 2, LBRT_FP16: 2}
@@ -45,6 +46,7 @@ class lbrt_desc(ctypes.Structure):
         ("lambda_iters", ctypes.c_int32),
         ("lambda_aniso", ctypes.c_double),
         ("moving_fluid", ctypes.c_int32),
+        ("rounding", ctypes.c_int32),
     ]
 
 
@@ -130,7 +132,7 @@ class Desc:
                  bc: Sequence[int] = (LBRT_BC_OUTFLOW,) * 6, dx: float = 1.0,
                  storage: int = LBRT_FP32, collision: int = LBRT_COLL_IMPLICIT,
                  lambda_iters: int = 5, lam: float = 0.0, moving_fluid: bool = False,
-                 scale=None):
+                 scale=None, rounding: int = LBRT_ROUND_STOCHASTIC):
         self.dirs = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
         self.weights = np.ascontiguousarray(weights, dtype=np.float64).reshape(-1)
         self.scale = None if scale is None else np.ascontiguousarray(scale, dtype=np.float64)
@@ -149,6 +151,7 @@ class Desc:
         d.lambda_iters = int(lambda_iters)
         d.lambda_aniso = float(lam)
         d.moving_fluid = 1 if moving_fluid else 0
+        d.rounding = int(rounding)
         self.c = d
 
     @property

@@ -25,6 +25,10 @@ FLAGS = [
     "-O3", "-std=c++20", "-fPIC", f"--offload-arch={ARCH}",
     # no packed FP32 (v_pk_*_f32) code generation
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no implicit fusing of a * b + c: every fused multiply-add in the kernels
+    # is an explicit fma(), so each kernel path rounds a cell's arithmetic the
+    # same way (the checked and the interior paths give the same bits)
+    "-ffp-contract=off",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 

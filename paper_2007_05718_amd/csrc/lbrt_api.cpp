@@ -81,12 +81,18 @@ struct lbrt_ctx {
   TileShape tile{64, 1};
   int zlen = 64;                  // z-planes per block of the main kernel
   int zlen_general = 4;           // z-planes per block of the general kernel
-  // General-kernel tile lists (device, int4 per block), for calls without
-  // (index 0) and with (index 1) inflow ghost planes on a z face.
-  int4 *general_dev[2] = {nullptr, nullptr};
-  std::vector<int4> general_host[2];
-  int ngeneral[2] = {0, 0};
-  int main_zr0[2] = {0, 0}, main_nzr[2] = {0, 0};
+  // Tile plans [mode][variant]: mode 0 runs the interior on the main kernel
+  // (one cell per lane), mode 1 on the pair kernel (two x cells per lane);
+  // variant 1 is for calls with inflow ghost planes on a z face.
+  struct Plan {
+    std::vector<GenTile> general;   // the general-path tiles
+    GenTile *dev = nullptr;         // the same, on the device
+    int zr0 = 0, nzr = 0;           // the main (or pair) kernel's z ranges
+  } plan[2][2];
+  bool pair = false;              // lbrt_step runs mode 1
+  PairTab *pair_tab_dev = nullptr;   // the pair kernel's slot records (nb each)
+  PairColl *pair_coll_dev = nullptr;
+  uint64_t round_seq = 0;         // steps taken: the stochastic rounding seeds
   int device = 0;
   unsigned char *scratch = nullptr;  // this device's scratch (lbrt_step_noalloc)
 };
@@ -124,19 +130,35 @@ TileShape default_tile(int nx, int ny, int nz) {
 
 // z-planes marched by one block: long enough that the prologue plane (one
 // extra plane per range) is cheap, short enough that the grid has several
-// blocks per CU.
-int default_zlen(int nx, int ny, int nz, const TileShape &t) {
+// blocks per CU: about `target` blocks (main kernel: 8192, 32 per CU, measured
+// fastest at 256^3; the pair kernel's blocks do twice the work: 4096), never
+// fewer than 16 planes.
+int default_zlen(int nz, int64_t xy_tiles, int64_t target) {
   if (const char *env = std::getenv("LBRT_ZLEN")) {
     const int v = std::atoi(env);
     if (v > 0) return v;
   }
-  const int64_t xy_tiles = (int64_t)((nx + t.tx - 1) / t.tx) * ((ny + t.ty - 1) / t.ty);
-  // aim for about 8192 blocks (32 per CU, measured fastest at 256^3) but
-  // never fewer than 16 planes
-  int64_t ranges = (8192 + xy_tiles - 1) / xy_tiles;
+  xy_tiles = std::max<int64_t>(xy_tiles, 1);
+  int64_t ranges = (target + xy_tiles - 1) / xy_tiles;
   int zlen = (int)std::max<int64_t>(16, (nz + ranges - 1) / ranges);
   return std::min(zlen, nz);
 }
+
+// The pair kernel computes x in [2, nx - 2) of rows [1, ny - 1), in tiles of
+// 128 cells at x = 128 k (whole cache lines).
+constexpr int kPairX0 = 2;
+constexpr int kPairTile = 128;
+int pair_ntx(int nx) { return (nx + kPairTile - 1) / kPairTile; }
+
+// A fixed random 32-bit constant per storage plane (splitmix64 of its index):
+// one of the three parts of an element's stochastic rounding bits.
+uint64_t splitmix64(uint64_t x) {
+  x += 0x9e3779b97f4a7c15ull;
+  x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+  x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+  return x ^ (x >> 31);
+}
+uint32_t plane_random(int plane) { return (uint32_t)(splitmix64(0x6c627274u + plane) >> 32); }
 
 // Direction table in processing order: nb slots (directions, then null
 // slots), stored twice (the step kernel reads copy z & 1 on plane z).
@@ -159,6 +181,9 @@ void build_table(const lbrt_ctx &c, std::vector<DirTab<T>> &tab) {
       e.plane_off = (int64_t)e.plane * ncell * esize;
       e.scale = T(1);
       e.inv_scale = T(1);
+      // a selector that merges two stored values (any other could assemble
+      // a NaN bit pattern, and 0 * NaN is not 0)
+      e.psel = 0x01000706u;
       continue;
     }
     const int i = c.order[k];
@@ -212,6 +237,8 @@ void build_table(const lbrt_ctx &c, std::vector<DirTab<T>> &tab) {
     e.plane_el = (int64_t)i * ncell;
     e.plane_off = (int64_t)i * ncell * esize;
     e.invw = e.w != T(0) ? T(1) / e.w : T(0);
+    e.psel = s[0] > 0 ? 0x05040302u : 0x01000706u;
+    e.rnd = plane_random(i);
   }
   // each slot carries its wave's sum of n_i w_i (the stored values, in FP64)
   const int m = c.nb / waves_for(c.nb);
@@ -221,6 +248,41 @@ void build_table(const lbrt_ctx &c, std::vector<DirTab<T>> &tab) {
       for (int a = 0; a < 3; ++a) nw[a] += (double)tab[k].n[a] * (double)tab[k].w;
     for (int k = q * m; k < (q + 1) * m; ++k)
       for (int a = 0; a < 3; ++a) tab[k].nwq[a] = nw[a];
+  }
+}
+
+// The pair kernel's compact slot records, from the FP32 direction table.
+void build_pair_tables(const std::vector<DirTab<float>> &tab, std::vector<PairTab> &pt,
+                       std::vector<PairColl> &pc) {
+  pt.assign(tab.size(), PairTab{});
+  pc.assign(tab.size(), PairColl{});
+  for (size_t k = 0; k < tab.size(); ++k) {
+    const DirTab<float> &e = tab[k];
+    PairTab &a = pt[k];
+    a.wx0 = e.wx[0];
+    a.wx1 = e.wx[1];
+    a.wy0 = e.wy[0];
+    a.wy1 = e.wy[1];
+    a.wz_new = e.wz_new;
+    a.wz_old = e.wz_old;
+    a.w = e.w;
+    a.invw = e.invw;
+    a.n0 = e.n[0];
+    a.n1 = e.n[1];
+    a.n2 = e.n[2];
+    a.scale = e.scale;
+    a.plane_off = e.plane_off;
+    a.row_off = (int32_t)e.row_off;
+    a.flags = (e.s[0] > 0 ? kPairSxPos : 0u) | (e.dzn ? kPairDzn : 0u) |
+              (e.active ? kPairActive : 0u);
+    PairColl &b = pc[k];
+    b.w = e.w;
+    b.n0 = e.n[0];
+    b.n1 = e.n[1];
+    b.n2 = e.n[2];
+    b.inv_scale = e.active ? e.inv_scale : 0.0f;   // 0 marks a padding slot
+    b.rnd = e.rnd;
+    b.plane_off = e.plane_off;
   }
 }
 
@@ -248,7 +310,8 @@ int ensure_partials(lbrt_ctx *c, int nblocks) {
   return LBRT_OK;
 }
 
-KParams make_params(const lbrt_ctx *c) {
+// Kernel parameters of the context for tile plan `mode` (variant 0).
+KParams make_params(const lbrt_ctx *c, int mode) {
   const lbrt_desc &d = c->desc;
   KParams p{};
   p.nx = d.nx;
@@ -261,17 +324,28 @@ KParams make_params(const lbrt_ctx *c) {
   p.txlog = 0;
   while ((1 << p.txlog) < p.tx) ++p.txlog;
   p.zlen = c->zlen;
-  // main kernel: every x tile (a ragged last tile masks its extra lanes), y
-  // tiles whose halo rows are inside the box
-  p.ntx = (d.nx + p.tx - 1) / p.tx;
   p.nty = (d.ny + p.ty - 1) / p.ty;
   p.main_ty0 = 1;
-  p.main_nty = std::max(0, (d.ny - 1 - p.ty) / p.ty);
-  p.main_zr0 = c->main_zr0[0];
-  p.main_nzr = c->main_nzr[0];
+  if (mode == 1) {
+    p.pair = 1;
+    p.pair_x0 = kPairX0;
+    p.pair_xend = d.nx - kPairX0;
+    p.pair_tab = c->pair_tab_dev;
+    p.pair_coll = c->pair_coll_dev;
+    p.ntx = pair_ntx(d.nx);
+    p.main_nty = d.ny - 2;
+  } else {
+    // main kernel: every x tile (a ragged last tile masks its extra lanes), y
+    // tiles whose halo rows are inside the box
+    p.ntx = (d.nx + p.tx - 1) / p.tx;
+    p.main_nty = std::max(0, (d.ny - 1 - p.ty) / p.ty);
+  }
+  const lbrt_ctx::Plan &pl = c->plan[mode][0];
+  p.main_zr0 = pl.zr0;
+  p.main_nzr = pl.nzr;
   p.nblocks = p.ntx * p.main_nty * p.main_nzr;
-  p.ngeneral = c->ngeneral[0];
-  p.general_list = c->general_dev[0];
+  p.ngeneral = (int)pl.general.size();
+  p.general_list = pl.dev;
   for (int a = 0; a < 3; ++a) p.periodic[a] = d.bc[2 * a] == LBRT_BC_PERIODIC;
   p.mode = d.collision;
   p.lambda_iters = d.lambda_iters;
@@ -280,55 +354,116 @@ KParams make_params(const lbrt_ctx *c) {
   if (d.moving_fluid) p.flags |= KF_MOVING;
   if (d.lambda_aniso == 0.0) p.flags |= KF_LAMZERO;
   if (c->nwq_zero) p.flags |= KF_NWQZERO;
+  if ((d.storage == LBRT_BF16 || d.storage == LBRT_FP16) && d.rounding == LBRT_ROUND_STOCHASTIC)
+    p.flags |= KF_STOCH;
   p.dt = d.dt;  // time step in length units (c = 1)
   p.lam = d.lambda_aniso;
   return p;
 }
 
+KParams make_params(const lbrt_ctx *c) { return make_params(c, c->pair ? 1 : 0); }
 
-// Splits the tiles between the main kernel (interior rows, full x tiles, z
-// ranges of zlen planes) and the general kernel (everything else, in z ranges
-// of zlen_general planes).  With zinflow, the first/last z range (next to a z
-// face with inflow ghost planes) also goes to the general kernel.
-int plan_tiles(lbrt_ctx *c, int variant, bool zlo_inflow, bool zhi_inflow) {
+// The same with the tile plan variant for inflow ghost planes on a z face.
+void use_zinflow_variant(const lbrt_ctx *c, KParams &p) {
+  const lbrt_ctx::Plan &pl = c->plan[p.pair ? 1 : 0][1];
+  p.main_zr0 = pl.zr0;
+  p.main_nzr = pl.nzr;
+  p.nblocks = p.ntx * p.main_nty * p.main_nzr;
+  p.ngeneral = (int)pl.general.size();
+  p.general_list = pl.dev;
+}
+
+// Splits the cells between the main (mode 0) or pair (mode 1) kernel and the
+// general kernel, which takes everything else in z ranges of zlen_general
+// planes.  Mode 0: main tiles are the context's xy tiles of the interior rows
+// (every x); mode 1: pair tiles cover x in [2, nx - 2) of rows [1, ny - 1),
+// and the general kernel takes the columns x < 2 and x >= nx - 2 (2 x 32
+// tiles) and the rows 0 and ny - 1.  With zlo_inflow / zhi_inflow, the first
+// / last z range (next to a z face with inflow ghost planes) of the interior
+// goes to the general kernel too.
+int plan_tiles(lbrt_ctx *c, int mode, int variant, bool zlo_inflow, bool zhi_inflow) {
   const lbrt_desc &d = c->desc;
   const int tx = c->tile.tx, ty = c->tile.ty;
-  const int ntx_all = (d.nx + tx - 1) / tx;
-  const int nty = (d.ny + ty - 1) / ty;
-  const int main_nty = std::max(0, (d.ny - 1 - ty) / ty);
+  int txlog = 0;
+  while ((1 << txlog) < tx) ++txlog;
   const int nzr = (d.nz + c->zlen - 1) / c->zlen;
   int zr0 = zlo_inflow ? 1 : 0;
   int zr1 = nzr - (zhi_inflow ? 1 : 0);
-  if (zr1 < zr0 || main_nty == 0) zr1 = zr0;
-  c->main_zr0[variant] = zr0;
-  c->main_nzr[variant] = zr1 - zr0;
+  const bool rows = mode == 1 ? d.ny > 2 : std::max(0, (d.ny - 1 - ty) / ty) > 0;
+  if (zr1 < zr0 || !rows) zr1 = zr0;
+  lbrt_ctx::Plan &pl = c->plan[mode][variant];
+  pl.zr0 = zr0;
+  pl.nzr = zr1 - zr0;
   const bool any_main = zr1 > zr0;
-  std::vector<int4> list;
-  auto add_column = [&](int tix, int tiy, int z0, int z1) {
-    for (int zb = z0; zb < z1; zb += c->zlen_general)
-      list.push_back(make_int4(tix * tx, tiy * ty, zb, std::min(z1, zb + c->zlen_general)));
+  const int zm0 = std::min(d.nz, zr0 * c->zlen), zm1 = std::min(d.nz, zr1 * c->zlen);
+  std::vector<GenTile> list;
+  auto add = [&](int x0, int y0, int xe, int ye, int tl, int z0, int z1) {
+    for (int zb = z0; zb < z1; zb += c->zlen_general) {
+      GenTile g{};
+      g.x0 = x0;
+      g.y0 = y0;
+      g.zb = zb;
+      g.ze = std::min(z1, zb + c->zlen_general);
+      g.xe = xe;
+      g.ye = ye;
+      g.txlog = tl;
+      list.push_back(g);
+    }
   };
-  for (int tiy = 0; tiy < nty; ++tiy) {
-    for (int tix = 0; tix < ntx_all; ++tix) {
-      const bool main_xy = any_main && tiy >= 1 && tiy <= main_nty;
-      if (!main_xy) {
-        add_column(tix, tiy, 0, d.nz);
-      } else {
-        add_column(tix, tiy, 0, std::min(d.nz, zr0 * c->zlen));
-        add_column(tix, tiy, std::min(d.nz, zr1 * c->zlen), d.nz);
+  if (mode == 0) {
+    const int ntx_all = (d.nx + tx - 1) / tx;
+    const int nty = (d.ny + ty - 1) / ty;
+    const int main_nty = std::max(0, (d.ny - 1 - ty) / ty);
+    for (int tiy = 0; tiy < nty; ++tiy) {
+      for (int tix = 0; tix < ntx_all; ++tix) {
+        const bool main_xy = any_main && tiy >= 1 && tiy <= main_nty;
+        if (!main_xy) {
+          add(tix * tx, tiy * ty, d.nx, d.ny, txlog, 0, d.nz);
+        } else {
+          add(tix * tx, tiy * ty, d.nx, d.ny, txlog, 0, zm0);
+          add(tix * tx, tiy * ty, d.nx, d.ny, txlog, zm1, d.nz);
+        }
+      }
+    }
+  } else {
+    const int xa = kPairX0, xb = d.nx - kPairX0;
+    // the face columns, every row
+    for (int x0 : {0, xb})
+      for (int y0 = 0; y0 < d.ny; y0 += 32) add(x0, y0, x0 + kPairX0, d.ny, 1, 0, d.nz);
+    // rows 0 and ny - 1 between them, and the interior rows' z ranges that
+    // the pair kernel does not march
+    for (int y = 0; y < d.ny; ++y) {
+      const bool face_row = y == 0 || y == d.ny - 1;
+      for (int x0 = xa; x0 < xb; x0 += 64) {
+        if (face_row || !any_main) {
+          add(x0, y, xb, y + 1, 6, 0, d.nz);
+        } else {
+          add(x0, y, xb, y + 1, 6, 0, zm0);
+          add(x0, y, xb, y + 1, 6, zm1, d.nz);
+        }
       }
     }
   }
-  c->ngeneral[variant] = (int)list.size();
-  c->general_host[variant] = list;
-  if (c->general_dev[variant]) (void)hipFree(c->general_dev[variant]);
-  c->general_dev[variant] = nullptr;
+  pl.general = list;
+  if (pl.dev) (void)hipFree(pl.dev);
+  pl.dev = nullptr;
   if (list.empty()) return LBRT_OK;
-  hipError_t e = hipMalloc(&c->general_dev[variant], sizeof(int4) * list.size());
+  hipError_t e = hipMalloc(&pl.dev, sizeof(GenTile) * list.size());
   if (e == hipSuccess)
-    e = hipMemcpy(c->general_dev[variant], list.data(), sizeof(int4) * list.size(),
-                  hipMemcpyHostToDevice);
+    e = hipMemcpy(pl.dev, list.data(), sizeof(GenTile) * list.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) return fail(LBRT_E_NOMEM, "tile list: %s", hipGetErrorString(e));
+  return LBRT_OK;
+}
+
+// Both modes' plans, both variants (mode 1 only where the pair kernel runs).
+int plan_all(lbrt_ctx *c) {
+  const lbrt_desc &d = c->desc;
+  const bool zlo = d.bc[LBRT_FACE_MZ] == LBRT_BC_INFLOW, zhi = d.bc[LBRT_FACE_PZ] == LBRT_BC_INFLOW;
+  for (int mode = 0; mode < (c->pair ? 2 : 1); ++mode) {
+    int rc = plan_tiles(c, mode, 0, false, false);
+    if (rc == LBRT_OK) rc = plan_tiles(c, mode, 1, zlo, zhi);
+    if (rc != LBRT_OK) return rc;
+  }
   return LBRT_OK;
 }
 
@@ -416,14 +551,8 @@ int prepare_step(lbrt_ctx *c, void *I_a, void *I_b, const float *kappa_a, const 
   KParams &p = call.p;
   p = make_params(c);
   if (xghosts) p.flags |= KF_XGHOSTS;
-  if (zghosts) {
-    // z ranges next to an inflow z face go to the general kernel
-    p.main_zr0 = c->main_zr0[1];
-    p.main_nzr = c->main_nzr[1];
-    p.nblocks = p.ntx * p.main_nty * p.main_nzr;
-    p.ngeneral = c->ngeneral[1];
-    p.general_list = c->general_dev[1];
-  }
+  // z ranges next to an inflow z face go to the general kernel
+  if (zghosts) use_zinflow_variant(c, p);
   call.launch = step_launcher(d.storage, c->bucket, d.moving_fluid != 0);
   if (!call.launch)
     return fail(LBRT_E_UNSUPPORTED, "no kernel for storage %d, %d directions", d.storage,
@@ -461,6 +590,8 @@ int run_steps(lbrt_ctx *c, const StepCall &call, void *I_a, void *I_b, const flo
     const void *src = (k & 1) ? I_b : I_a;
     void *dst = (k & 1) ? I_a : I_b;
     KParams pk = p;
+    // this step's stochastic rounding seed (one per step of the context)
+    pk.seed = (uint32_t)splitmix64(0x5eedull ^ (c->round_seq++ * 0x9e3779b97f4a7c15ull));
     const bool last = k == nsteps - 1;
     if (diag) {
       pk.flags |= KF_DIAG;
@@ -518,6 +649,8 @@ int lbrt_validate(const lbrt_desc *d) {
     return fail(LBRT_E_INVAL, "storage = %d is not a storage type", d->storage);
   if (d->collision < LBRT_COLL_IMPLICIT || d->collision > LBRT_COLL_LAMBDA)
     return fail(LBRT_E_INVAL, "collision = %d is not a collision kind", d->collision);
+  if (d->rounding != LBRT_ROUND_STOCHASTIC && d->rounding != LBRT_ROUND_NEAREST)
+    return fail(LBRT_E_INVAL, "rounding = %d is not a rounding mode", d->rounding);
   if (d->collision == LBRT_COLL_LAMBDA && d->lambda_iters < 1)
     return fail(LBRT_E_INVAL, "lambda_iters must be >= 1");
   if (!std::isfinite(d->lambda_aniso)) return fail(LBRT_E_INVAL, "lambda_aniso not finite");
@@ -612,7 +745,6 @@ int lbrt_init(const lbrt_desc *d, lbrt_ctx **out) {
   }
   c->paired = paired;
   c->tile = default_tile(d->nx, d->ny, d->nz);
-  c->zlen = default_zlen(d->nx, d->ny, d->nz, c->tile);
   if (const char *env = std::getenv("LBRT_ZLEN_GENERAL")) {
     const int v = std::atoi(env);
     if (v > 0) c->zlen_general = v;
@@ -657,6 +789,17 @@ int lbrt_init(const lbrt_desc *d, lbrt_ctx **out) {
     c->tab_bytes = tab_bytes;
     e = hipMalloc(&c->tab_dev, tab_bytes);
     if (e == hipSuccess) e = hipMemcpy(c->tab_dev, tab.data(), tab_bytes, hipMemcpyHostToDevice);
+    std::vector<PairTab> pt;
+    std::vector<PairColl> pcl;
+    build_pair_tables(tab, pt, pcl);
+    if (e == hipSuccess) e = hipMalloc(&c->pair_tab_dev, sizeof(PairTab) * pt.size());
+    if (e == hipSuccess)
+      e = hipMemcpy(c->pair_tab_dev, pt.data(), sizeof(PairTab) * pt.size(),
+                    hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&c->pair_coll_dev, sizeof(PairColl) * pcl.size());
+    if (e == hipSuccess)
+      e = hipMemcpy(c->pair_coll_dev, pcl.data(), sizeof(PairColl) * pcl.size(),
+                    hipMemcpyHostToDevice);
   }
   if (e == hipSuccess) e = hipMalloc(&c->scales_dev, sizeof(double) * d->ndir);
   if (e == hipSuccess)
@@ -668,11 +811,21 @@ int lbrt_init(const lbrt_desc *d, lbrt_ctx **out) {
     lbrt_destroy(c);
     return rc;
   }
-  rc = plan_tiles(c, 0, false, false);
-  if (rc == LBRT_OK) {
-    const bool zlo = d->bc[LBRT_FACE_MZ] == LBRT_BC_INFLOW, zhi = d->bc[LBRT_FACE_PZ] == LBRT_BC_INFLOW;
-    rc = (zlo || zhi) ? plan_tiles(c, 1, zlo, zhi) : plan_tiles(c, 1, false, false);
+  // The pair kernel (two x cells per lane) runs the interior where it is
+  // compiled, on grids with even nx, for rules whose flux sums need no FP64
+  // reference term; LBRT_PAIR=0 keeps the main kernel (speed only).
+  {
+    const char *env = std::getenv("LBRT_PAIR");
+    c->pair = pair_available(d->storage, c->nb, d->moving_fluid != 0) && d->nx % 2 == 0 &&
+              d->nx >= 8 && d->ny >= 3 && c->nwq_zero && !(env && std::strcmp(env, "0") == 0);
   }
+  {
+    const int64_t xy = c->pair ? (int64_t)pair_ntx(d->nx) * (d->ny - 2)
+                               : (int64_t)((d->nx + c->tile.tx - 1) / c->tile.tx) *
+                                     ((d->ny + c->tile.ty - 1) / c->tile.ty);
+    c->zlen = default_zlen(d->nz, xy, c->pair ? 4096 : 8192);
+  }
+  rc = plan_all(c);
   if (rc != LBRT_OK) {
     lbrt_destroy(c);
     return rc;
@@ -701,11 +854,14 @@ int lbrt_init(const lbrt_desc *d, lbrt_ctx **out) {
 void lbrt_destroy(lbrt_ctx *c) {
   if (!c) return;
   if (c->tab_dev) (void)hipFree(c->tab_dev);
+  if (c->pair_tab_dev) (void)hipFree(c->pair_tab_dev);
+  if (c->pair_coll_dev) (void)hipFree(c->pair_coll_dev);
   if (c->scales_dev) (void)hipFree(c->scales_dev);
   if (c->partials) (void)hipFree(c->partials);
   if (c->inflow_dev) (void)hipFree(c->inflow_dev);
-  for (int v = 0; v < 2; ++v)
-    if (c->general_dev[v]) (void)hipFree(c->general_dev[v]);
+  for (auto &m : c->plan)
+    for (auto &pl : m)
+      if (pl.dev) (void)hipFree(pl.dev);
   if (c->adj_work) (void)hipFree(c->adj_work);
   delete c;
 }
@@ -847,6 +1003,7 @@ struct lbrt_batch {
   // device allocations
   BatchDomain *dom = nullptr;
   int4 *tiles = nullptr;
+  GenTile *gtiles = nullptr;
   long long *main_prefix = nullptr, *gen_prefix = nullptr;
   char *tabs = nullptr;
   int32_t *step_active = nullptr;
@@ -865,11 +1022,7 @@ int lbrt_set_tiling(lbrt_ctx *c, int32_t tx, int32_t ty, int32_t zlen, int32_t z
   c->tile = TileShape{tx, ty};
   c->zlen = std::min(zlen, d.nz);
   c->zlen_general = zlen_general;
-  int rc = plan_tiles(c, 0, false, false);
-  if (rc == LBRT_OK) {
-    const bool zlo = d.bc[LBRT_FACE_MZ] == LBRT_BC_INFLOW, zhi = d.bc[LBRT_FACE_PZ] == LBRT_BC_INFLOW;
-    rc = plan_tiles(c, 1, zlo, zhi);
-  }
+  int rc = plan_all(c);
   if (rc != LBRT_OK) return rc;
   KParams p = make_params(c);
   return ensure_partials(c, total_partials(p));
@@ -887,8 +1040,8 @@ int lbrt_get_tiling(const lbrt_ctx *c, int32_t *tx, int32_t *ty, int32_t *zlen,
 
 void lbrt_batch_destroy(lbrt_batch *b) {
   if (!b) return;
-  void *ptrs[] = {b->dom, b->tiles, b->tabs, b->main_prefix, b->gen_prefix, b->step_active,
-                  b->noinflow};
+  void *ptrs[] = {b->dom, b->tiles, b->gtiles, b->tabs, b->main_prefix, b->gen_prefix,
+                  b->step_active, b->noinflow};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   delete b;
@@ -926,13 +1079,15 @@ int lbrt_batch_create(const lbrt_domain *domains, int32_t ndomains, lbrt_batch *
                    [&](int a, int b) { return domains[a].nsteps > domains[b].nsteps; });
   std::vector<BatchDomain> dom(ndomains);
   std::vector<int4> tiles;
+  std::vector<GenTile> gtiles;
   std::vector<long long> mprefix(ndomains + 1, 0), gprefix(ndomains + 1, 0);
-  std::vector<size_t> tile_start(ndomains), tab_start(ndomains);
+  std::vector<size_t> tile_start(ndomains), gtile_start(ndomains), tab_start(ndomains);
   size_t tab_total = 0;
   for (int j = 0; j < ndomains; ++j) {
     const lbrt_domain &D = domains[order[j]];
     const lbrt_ctx *c = D.ctx;
-    KParams p = make_params(c);
+    // the batched kernels run the interior on the main kernel (plan mode 0)
+    KParams p = make_params(c, 0);
     tile_start[j] = tiles.size();
     for (int zr = p.main_zr0; zr < p.main_zr0 + p.main_nzr; ++zr)
       for (int ty = p.main_ty0; ty < p.main_ty0 + p.main_nty; ++ty)
@@ -941,17 +1096,19 @@ int lbrt_batch_create(const lbrt_domain *domains, int32_t ndomains, lbrt_batch *
           tiles.push_back(make_int4(tx * p.tx, ty * p.ty, zb, std::min(p.nz, zb + p.zlen)));
         }
     const int32_t nmain = (int32_t)(tiles.size() - tile_start[j]);
-    for (const int4 &w : c->general_host[0]) tiles.push_back(w);
+    gtile_start[j] = gtiles.size();
+    for (const GenTile &g : c->plan[0][0].general) gtiles.push_back(g);
+    const int32_t ngen = (int32_t)(gtiles.size() - gtile_start[j]);
     BatchDomain &B = dom[j];
     B.p = p;
     B.p.flags &= ~(uint32_t)(KF_DIAG | KF_WRITE_EF | KF_XGHOSTS);
     tab_start[j] = tab_total;
     tab_total += (c->tab_bytes + 255) / 256 * 256;
-    B.ntiles = (int32_t)(tiles.size() - tile_start[j]);
+    B.ntiles = nmain + ngen;
     B.nmain = nmain;
     B.nsteps = D.nsteps;
     mprefix[j + 1] = mprefix[j] + nmain;
-    gprefix[j + 1] = gprefix[j] + (B.ntiles - nmain);
+    gprefix[j + 1] = gprefix[j] + ngen;
   }
   const int maxsteps = domains[order[0]].nsteps;
   std::vector<int32_t> active(std::max(maxsteps, 1), 0);
@@ -979,6 +1136,7 @@ int lbrt_batch_create(const lbrt_domain *domains, int32_t ndomains, lbrt_batch *
     if (e == hipSuccess && bytes) e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
   };
   up((void **)&b->tiles, tiles.data(), sizeof(int4) * tiles.size());
+  up((void **)&b->gtiles, gtiles.data(), sizeof(GenTile) * gtiles.size());
   // the domains' direction tables, one block
   if (e == hipSuccess) e = hipMalloc((void **)&b->tabs, std::max<size_t>(tab_total, 256));
   for (int j = 0; j < ndomains && e == hipSuccess; ++j) {
@@ -996,6 +1154,7 @@ int lbrt_batch_create(const lbrt_domain *domains, int32_t ndomains, lbrt_batch *
       const lbrt_domain &D = domains[order[j]];
       BatchDomain &B = dom[j];
       B.tiles = b->tiles + tile_start[j];
+      B.gtiles = b->gtiles + gtile_start[j];
       B.tab = (int64_t)tab_start[j];
       B.I[0] = off(D.I_a);
       B.I[1] = off(D.I_b);

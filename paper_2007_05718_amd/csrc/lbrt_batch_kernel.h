@@ -36,7 +36,7 @@ __device__ __forceinline__ void batch_item(const BatchPlan &bp, const char *__re
   // fields, pointers and direction table are read with scalar loads
   a = __builtin_amdgcn_readfirstlane(a);
   const BatchDomain &D = bp.dom[a];
-  const int t = __builtin_amdgcn_readfirstlane((int)(l - prefix[a]) + (MAIN ? 0 : D.nmain));
+  const int t = __builtin_amdgcn_readfirstlane((int)(l - prefix[a]));
   KParams p = D.p;
   const bool last = s == D.nsteps - 1;
   if (last && (D.E != kNoBuffer || D.F != kNoBuffer)) p.flags |= KF_WRITE_EF;
@@ -54,18 +54,30 @@ __device__ __forceinline__ void batch_item(const BatchPlan &bp, const char *__re
   const S *Iin = reinterpret_cast<const S *>(gbase + u64(D.I[s & 1]));
   S *Iout = reinterpret_cast<S *>(gbase + u64(D.I[(s + 1) & 1]));
   const DirTab<T> *tab = reinterpret_cast<const DirTab<T> *>(tabs + u64(D.tab));
-  int4 w = D.tiles[t];
-  w.x = __builtin_amdgcn_readfirstlane(w.x);
-  w.y = __builtin_amdgcn_readfirstlane(w.y);
-  w.z = __builtin_amdgcn_readfirstlane(w.z);
-  w.w = __builtin_amdgcn_readfirstlane(w.w);
+  // the tile: main tiles are (x0, y0, zb, ze) of the context's tile shape,
+  // general ones carry their own shape and bounds
+  int x0, y0, zb, ze, txlog = p.txlog, xe = p.nx, ye = p.ny;
+  if constexpr (MAIN) {
+    const int4 w = D.tiles[t];
+    x0 = w.x, y0 = w.y, zb = w.z, ze = w.w;
+  } else {
+    const GenTile g = D.gtiles[t];
+    x0 = g.x0, y0 = g.y0, zb = g.zb, ze = g.ze, txlog = g.txlog, xe = g.xe, ye = g.ye;
+  }
+  x0 = __builtin_amdgcn_readfirstlane(x0);
+  y0 = __builtin_amdgcn_readfirstlane(y0);
+  zb = __builtin_amdgcn_readfirstlane(zb);
+  ze = __builtin_amdgcn_readfirstlane(ze);
+  txlog = __builtin_amdgcn_readfirstlane(txlog);
+  xe = __builtin_amdgcn_readfirstlane(xe);
+  ye = __builtin_amdgcn_readfirstlane(ye);
   T *E = last ? reinterpret_cast<T *>(buf(D.E)) : nullptr;
   T *F = last ? reinterpret_cast<T *>(buf(D.F)) : nullptr;
   march<S, NB, MOVING, MAIN>(Iin, Iout, reinterpret_cast<const float *>(gbase + u64(D.ka)),
                              reinterpret_cast<const float *>(gbase + u64(D.ks)),
                              reinterpret_cast<const float *>(gbase + u64(D.eta)),
                              reinterpret_cast<const float *>(buf(D.vel)), tab, p, bp.noinflow,
-                             E, F, nullptr, w.x, w.y, w.z, w.w);
+                             E, F, nullptr, x0, y0, zb, ze, txlog, xe, ye);
 }
 
 template <typename S, int NB, bool MOVING>

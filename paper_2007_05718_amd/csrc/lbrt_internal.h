@@ -55,6 +55,49 @@ struct DirTab {
   T delta[3];       // dt |n^a| / dx, the fraction pulled from the upwind cell
   int32_t s[3];     // shift signs sgn(n^a), 0 where n^a == 0
   int32_t plane;    // storage plane (direction index in the caller's order)
+  // Pair kernels, 16-bit storage: byte selector of v_perm_b32 that forms the
+  // x-shifted pair of cells from the lane's own pair and its neighbouring
+  // pair (sx > 0: (neighbour.hi, own.lo); otherwise (own.hi, neighbour.lo)).
+  uint32_t psel;
+  // Stochastic rounding of 16-bit storage: a random 32-bit constant of the
+  // direction's storage plane (the element's random bits are this, the
+  // cell's hash and the step's seed, combined by exclusive or).
+  uint32_t rnd;
+};
+
+// Compact per-slot records of the pair kernel, read once per plane with one
+// wide scalar load each (the full DirTab of 112 slots outgrows the scalar
+// cache): the streaming phase's constants, and the collision's.
+struct PairTab {                     // 64 bytes
+  float wx0, wx1, wy0, wy1;          // per-axis interpolation weights (eq. interp)
+  float wz_new, wz_old;              // z weights in march order (see DirTab)
+  float w, invw;                     // quadrature weight and 1 / w (0 for a null slot)
+  float n0, n1, n2;                  // unit direction
+  float scale;                       // storage scale s_i (1 for FP32)
+  int64_t plane_off;                 // byte offset of the direction's plane
+  int32_t row_off;                   // byte offset of the y-halo row (-sy nx cells)
+  uint32_t flags;                    // kPairSxPos | kPairDzn | kPairActive
+};
+struct PairColl {                    // 32 bytes
+  float w, n0, n1, n2;
+  float inv_scale;                   // 1 / s_i
+  uint32_t rnd;                      // the plane's stochastic-rounding constant
+  int64_t plane_off;
+};
+static_assert(sizeof(PairTab) == 64 && sizeof(PairColl) == 32,
+              "one wide scalar load per record");
+enum : uint32_t {
+  kPairSxPos = 1u << 0,              // sx > 0: the x-shifted taps lie at x - 1
+  kPairDzn = 1u << 1,                // sz < 0: the new plane is the one above
+  kPairActive = 1u << 2,             // a direction (not a padding slot)
+};
+
+// A tile of the general (checked) path: 64 cells in a 2^txlog x 2^(6-txlog)
+// xy block at (x0, y0), cells outside [x0, xe) x [y0, ye) inactive, marched
+// over z planes [zb, ze).
+struct GenTile {
+  int32_t x0, y0, zb, ze;
+  int32_t xe, ye, txlog, pad;
 };
 
 // Inflow ghost planes of one call, kept in device memory (context-owned) so
@@ -93,6 +136,7 @@ enum : uint32_t {
   KF_LAMZERO = 1u << 4,  // lambda == 0 (anisotropic term skipped)
   KF_XGHOSTS = 1u << 5,  // some inflow ghost plane sits on an x face
   KF_NWQZERO = 1u << 6,  // every wave's sum of n_i w_i is exactly 0
+  KF_STOCH = 1u << 7,    // 16-bit storage rounds stochastically (seed below)
 };
 
 struct KParams {
@@ -107,13 +151,22 @@ struct KParams {
   // z ranges [main_zr0, main_zr0 + main_nzr); nblocks = ntx * main_nty * main_nzr.
   int32_t main_ty0, main_nty, main_zr0, main_nzr;
   int32_t nblocks;
-  // General kernel: one block per (x0, y0, zb, ze) entry.
+  // General kernel: one block per GenTile entry.
   int32_t ngeneral;
-  const int4 *general_list;
+  const GenTile *general_list;
+  // Pair kernel (two x cells per lane) in place of the main kernel: tiles of
+  // 128 cells at x0 = 128 k (k < ntx) computing the cells x in
+  // [pair_x0, pair_xend) of rows [main_ty0, main_ty0 + main_nty), the same z
+  // ranges.
+  int32_t pair;
+  int32_t pair_x0, pair_xend;
+  const PairTab *pair_tab;     // the pair kernel's slot records (nb of each)
+  const PairColl *pair_coll;
   int32_t periodic[3];         // per axis x, y, z
   int32_t mode;                // lbrt_collision
   int32_t lambda_iters;
   uint32_t flags;
+  uint32_t seed;               // this step's random seed (KF_STOCH)
   double dt;
   double lam;
 };
@@ -142,6 +195,9 @@ using StepLauncher = hipError_t (*)(const void *Iin, void *Iout, const float *ka
                                     double *partials, hipStream_t s);
 
 StepLauncher step_launcher(int storage, int bucket_index, bool moving);
+// Whether the step launcher of (storage, bucket size, fluid) has the pair
+// kernel (KParams::pair).
+bool pair_available(int storage, int nb, bool moving);
 
 // ---------------------------------------------------------------------------
 // Batched form (one persistent launch over many domains)
@@ -158,8 +214,8 @@ struct BatchDomain {
   int64_t I[2];           // ping-pong pair: step s reads I[s & 1]
   int64_t ka, ks, eta, vel;
   int64_t E, F;           // moments after the last step, or kNoBuffer
-  const int4 *tiles;      // (x0, y0, zb, ze): the nmain main-path tiles, then the
-                          // general-path ones
+  const int4 *tiles;      // (x0, y0, zb, ze): the nmain main-path tiles
+  const GenTile *gtiles;  // the general-path tiles
   int32_t ntiles, nmain;
   int32_t nsteps;
 };

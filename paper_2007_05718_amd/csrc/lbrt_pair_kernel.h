@@ -1,0 +1,401 @@
+// The fused step on interior tiles with two adjacent x cells per lane.
+//
+// A block owns a row segment of 128 cells (64 lanes, cells x0 + 2l and
+// x0 + 2l + 1 on lane l) and marches it through a range of z planes, like
+// the main kernel of lbrt_step_kernel.h, with its NW waves splitting the
+// direction slots.  Each slot's constants, addresses and loads then serve two
+// cells: a row load is one dword holding both cells' BF16 or FP16 values, so
+// a plane costs four loads per direction for two cells and one store.
+//
+// The x-shifted pair of a row, cells (x - sx, x + 1 - sx), comes from the
+// neighbouring pair (the one before it for sx > 0, after it otherwise; for
+// sx = 0 its weight is 0), an aligned load like the own pair, by one
+// v_perm_b32 of the two dwords with the slot's byte selector.
+//
+// Only the 16-bit forms take this path.  With FP32 storage a two-cell lane
+// holds twice the bytes per slot in flight, so under the same register
+// budget it keeps half as many slots ahead per cell and waits longer on its
+// loads than the one-cell main kernel; the main kernel serves FP32.
+// The slot constants come from compact records (PairTab, PairColl), each
+// read with one wide scalar load per plane.
+//
+// The tiles start at x = 128 k, so a wave's row loads and stores are whole
+// cache lines; they compute the cells x in [2, nx - 2) of rows [1, ny - 1),
+// where every tap of a row is inside the box and no cell is on an x or y
+// face.  The columns x < 2, x >= nx - 2 (whose pairs these tiles load but do
+// not store) and the face rows are tiles of the general (checked) path.  A
+// face pair's neighbouring pair lies in the row before or after, which
+// exists for interior rows.  nx is even, so every pair starts at an even
+// cell index and its loads and stores are aligned.
+//
+// Per plane:
+//   stream   the wave's slots for both cells (P from 4 row loads, issued a few
+//            slots ahead; I* from P and the carried plane value);
+//   moments  per-wave partial E*, F* of the 128 cells into LDS; barrier;
+//   combine  the 512 sums (4 moments x 128 cells) are split over the block:
+//            each lane forms one or two of them over the waves (a fixed
+//            pairwise order, the general path's), then the collision's E or
+//            F part for that cell (coef_E / coef_F), writes E or F, and puts
+//            c, alpha (and beta) in LDS; barrier;
+//   collide  every wave reads its cells' c, alpha (beta) and writes the new
+//            populations of its slots, one store per slot for both cells.
+// A cell gives the same bits here as on the general path: the same per-slot
+// arithmetic, the same summation order, the same collision functions and the
+// same random bits for stochastic rounding.
+#pragma once
+
+namespace lbrt {
+
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+template <typename S> struct PairIO;
+
+template <typename S> struct PairIO16 {
+  using R = uint32_t;
+  static constexpr uint32_t kShift = 4;   // byte offset of the neighbouring pair
+  __device__ static R ld(const char *b, uint32_t off) {
+    return *reinterpret_cast<const uint32_t *>(b + off);
+  }
+  // the x-shifted pair (nb.hi, own.lo) for sx > 0, else (own.hi, nb.lo)
+  __device__ static R shifted(R own, R nb, bool pos) {
+    return __builtin_amdgcn_perm(own, nb, pos ? 0x05040302u : 0x01000706u);
+  }
+};
+
+template <> struct PairIO<bf16_t> : PairIO16<bf16_t> {
+  __device__ static float lo(R v) { return __uint_as_float(v << 16); }
+  __device__ static float hi(R v) { return __uint_as_float(v & 0xffff0000u); }
+  // the shifted cells as FP32 bit patterns in one v_perm_b32 each: the BF16
+  // half into the high 16 bits, zeros (byte selector 0x0c) below
+  __device__ static float shifted_lo(R own, R nb, bool pos) {
+    return __uint_as_float(__builtin_amdgcn_perm(own, nb, pos ? 0x03020c0cu : 0x07060c0cu));
+  }
+  __device__ static float shifted_hi(R own, R nb, bool pos) {
+    return __uint_as_float(__builtin_amdgcn_perm(own, nb, pos ? 0x05040c0cu : 0x01000c0cu));
+  }
+  __device__ static void st(char *b, uint32_t off, float a, float c, uint32_t ra, uint32_t rc,
+                            bool sr) {
+    uint32_t w;
+    if (sr) {
+      s16x2 h = __builtin_amdgcn_cvt_sr_bf16_f32(s16x2{0, 0}, a, ra, false);
+      h = __builtin_amdgcn_cvt_sr_bf16_f32(h, c, rc, true);
+      w = __builtin_bit_cast(uint32_t, h);
+    } else {
+      typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+      w = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, c}, bf16x2));
+    }
+    __builtin_nontemporal_store(w, reinterpret_cast<uint32_t *>(b + off));
+  }
+};
+
+template <> struct PairIO<f16_t> : PairIO16<f16_t> {
+  __device__ static float lo(R v) {
+    return (float)__builtin_bit_cast(f16x2, v).x;
+  }
+  __device__ static float hi(R v) {
+    return (float)__builtin_bit_cast(f16x2, v).y;
+  }
+  __device__ static float shifted_lo(R own, R nb, bool pos) { return lo(shifted(own, nb, pos)); }
+  __device__ static float shifted_hi(R own, R nb, bool pos) { return hi(shifted(own, nb, pos)); }
+  __device__ static void st(char *b, uint32_t off, float a, float c, uint32_t ra, uint32_t rc,
+                            bool sr) {
+    f16x2 h;
+    if (sr) {
+      h = __builtin_amdgcn_cvt_sr_f16_f32(f16x2{0, 0}, a, ra, false);
+      h = __builtin_amdgcn_cvt_sr_f16_f32(h, c, rc, true);
+    } else {
+      h = __builtin_convertvector(f32x2{a, c}, f16x2);
+    }
+    __builtin_nontemporal_store(__builtin_bit_cast(uint32_t, h),
+                                reinterpret_cast<uint32_t *>(b + off));
+  }
+};
+
+// Compiled combinations: static fluid, BF16 / FP16 storage, the 56- and
+// 112-slot buckets.
+template <typename S, int NB, bool MOVING>
+constexpr bool pair_kernel_exists() {
+  return !MOVING && sizeof(S) == 2 && (NB == 56 || NB == 112);
+}
+
+// Slots whose four row loads (4 VGPRs) are in flight ahead of the slot being
+// interpolated.
+template <typename S>
+constexpr int pair_pf_depth(int m) {
+  return m < 4 ? m : 4;
+}
+
+// Plane value from four taps with the slot's per-axis weights: the same
+// rounding order as interp4.
+__device__ __forceinline__ float interp4w(const PairTab &d, float a, float a1, float b,
+                                          float b1) {
+  return lerp2(d.wy0, d.wy1, lerp2(d.wx0, d.wx1, a, a1), lerp2(d.wx0, d.wx1, b, b1));
+}
+
+// New population of one direction of a cell (collide_one with a PairColl).
+__device__ __forceinline__ float collide_pair(const PairColl &d, float c, float alpha, float b0,
+                                              float b1, float b2, float Is, bool lamzero) {
+  if (lamzero) return fma(c, Is, d.w * alpha);
+  const float nb = fma(d.n2, b2, fma(d.n1, b1, fma(d.n0, b0, alpha)));
+  return fma(c, Is, d.w * nb);
+}
+
+template <typename S, int NB, int NW = waves_for(NB)>
+__device__ __forceinline__ void
+march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__ ka,
+           const float *__restrict__ ks, const float *__restrict__ eta,
+           const PairTab *__restrict__ tab, const PairColl *__restrict__ ctab, const KParams &p,
+           float *__restrict__ Eout, float *__restrict__ Fout, double *__restrict__ partials,
+           int x0, int y, int zb, int ze) {
+  using IO = PairIO<S>;
+  using R = typename IO::R;
+  using T = float;
+  constexpr int SZ = (int)sizeof(S);
+  constexpr int M = NB / NW;
+  constexpr int NC = 128;                       // cells of a tile
+  constexpr int RI = 4 * NC / (64 * NW);        // combine items per lane
+  static_assert(4 * NC % (64 * NW) == 0, "combine items must split evenly");
+  constexpr int D = pair_pf_depth<S>(M);
+
+  const int nx = p.nx, nz = p.nz;
+  const int64_t pc = (int64_t)nx * p.ny;
+  const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int perz = p.periodic[2];
+  const int xend = p.pair_xend;
+  const T dt = (T)p.dt;
+  const bool diag = (p.flags & KF_DIAG) != 0;
+  const bool stoch = (p.flags & KF_STOCH) != 0;
+
+  // stream lanes: cells (x, x + 1), stored when inside [pair_x0, pair_xend);
+  // a lane beyond the row reads the last pair
+  int x = x0 + 2 * lane;
+  const bool valid = x >= p.pair_x0 && x < xend;
+  if (x >= xend) x = xend - 2;
+  const uint32_t o0 = (uint32_t)(x + nx * y) * (uint32_t)SZ;
+  // combine lanes: cell cc of the tile
+  const int cc = (q & 1) * 64 + lane;
+  int xc = x0 + cc;
+  const bool valid_c = xc >= p.pair_x0 && xc < xend;
+  if (xc >= xend) xc = xend - 1;
+  const uint32_t ocell = (uint32_t)(xc + nx * y);
+
+  const PairTab *__restrict__ tb = tab + q * M;
+  const char *const in_bytes = reinterpret_cast<const char *>(Iin);
+
+  // the four row loads of slot d from the z-plane starting at byte `plane`
+  // (rows y and y - sy; own and neighbouring pair)
+  // The neighbouring pair's shift goes into the wave-uniform base, so the
+  // four loads share the lane's offset o0 (scalar base + 32-bit lane offset).
+  auto load4 = [&](const PairTab &d, const char *plane, R (&v)[4]) {
+    const char *r0 = plane + d.plane_off;
+    const char *r1 = r0 + d.row_off;
+    const int sh = (d.flags & kPairSxPos) ? -(int)IO::kShift : (int)IO::kShift;
+    const uint32_t oo = opaque_lane(o0);
+    v[0] = IO::ld(r0, oo);
+    v[1] = IO::ld(r0 + sh, oo);
+    v[2] = IO::ld(r1, oo);
+    v[3] = IO::ld(r1 + sh, oo);
+  };
+  // plane values of both cells from a slot's four loads
+  auto interp2 = [&](const PairTab &d, const R (&v)[4], T &Plo, T &Phi) {
+    const bool pos = (d.flags & kPairSxPos) != 0;
+    Plo = interp4w(d, IO::lo(v[0]), IO::shifted_lo(v[0], v[1], pos), IO::lo(v[2]),
+                   IO::shifted_lo(v[2], v[3], pos));
+    Phi = interp4w(d, IO::hi(v[0]), IO::shifted_hi(v[0], v[1], pos), IO::hi(v[2]),
+                   IO::shifted_hi(v[2], v[3], pos));
+  };
+  auto plane_above = [&](int z) {
+    const int za = z + 1 < nz ? z + 1 : (perz ? 0 : nz - 1);
+    return (int64_t)za * pc;
+  };
+
+  // prologue: the carried plane value of every slot and both cells
+  T carry[M][2];
+  {
+    auto pro = [&]<int J>() {
+      const PairTab &d = tb[J];
+      carry[J][0] = carry[J][1] = T(0);
+      // (sz == 0: the carried plane has weight 0)
+      if (d.wz_old != T(0)) {
+        int zl = (d.flags & kPairDzn) ? zb : zb - 1;
+        if (perz) zl = wrap(zl, nz);
+        R v[4];
+        const bool in = (unsigned)zl < (unsigned)nz;
+        load4(d, in_bytes + (int64_t)min(max(zl, 0), nz - 1) * pc * SZ, v);
+        T a, b;
+        interp2(d, v, a, b);
+        carry[J][0] = (in ? T(1) : T(0)) * a;
+        carry[J][1] = (in ? T(1) : T(0)) * b;
+      }
+    };
+    unroll<0, M>(pro);
+  }
+
+  __shared__ T red[NW][4][NC];
+  __shared__ T coef[5][NC];
+  R pf[M][4];
+  auto issue_first = [&](int zn) {
+    const char *const p0 = in_bytes + (int64_t)zn * pc * SZ;
+    const char *const p1 = in_bytes + plane_above(zn) * SZ;
+    auto one = [&]<int J>() { load4(tb[J], (tb[J].flags & kPairDzn) ? p1 : p0, pf[J]); };
+    unroll<0, D>(one);
+  };
+  if (zb < ze) issue_first(zb);
+
+  // the combine lane's medium, loaded a plane ahead
+  T med[3];
+  auto load_medium = [&](int64_t cplane, uint32_t om) {
+    med[0] = ldo<float>(ka + cplane, om);
+    med[1] = ldo<float>(ks + cplane, om);
+    med[2] = ldo<float>(eta + cplane, om);
+  };
+  load_medium((int64_t)zb * pc, ocell * 4u);
+
+  double sE = 0.0, sEs = 0.0;
+  const T lam = (T)p.lam;
+  const bool lamzero = (p.flags & KF_LAMZERO) != 0;
+
+  for (int z = zb; z < ze; ++z) {
+    tb = tab + opaque(q * M);
+    const int64_t cz = (int64_t)z * pc;
+    const T kat = med[0], kst = med[1], et = med[2];
+    const int64_t cz_next = z + 1 < ze ? cz + pc : cz;
+    const uint32_t om = opaque_lane(ocell * 4u);
+
+    // ---- stream: both cells of every slot of this wave
+    T Is[M][2];
+    T Es[2] = {T(0), T(0)}, F0[2] = {T(0), T(0)}, F1[2] = {T(0), T(0)}, F2[2] = {T(0), T(0)};
+    T ref[2] = {T(0), T(0)};
+    {
+      const char *const p0 = in_bytes + cz * SZ;
+      const char *const p1 = in_bytes + plane_above(z) * SZ;
+      // plane above the box: vacuum (wave-uniform, so the zeroing is scalar)
+      const int gh = __builtin_amdgcn_readfirstlane((!perz && z + 1 >= nz) ? 1 : 0);
+      auto slot = [&]<int J>() {
+        const PairTab &d = tb[J];
+        if constexpr (J + D < M)
+          load4(tb[J + D], (tb[J + D].flags & kPairDzn) ? p1 : p0, pf[J + D]);
+        T Pn[2];
+        interp2(d, pf[J], Pn[0], Pn[1]);
+        const T wn = zero_if(d.wz_new, (int)((d.flags >> 1) & 1u) & gh);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          T sv = fma(d.wz_old, carry[J][h], wn * Pn[h]);
+          if constexpr (sizeof(S) == 2) sv *= d.scale;
+          Is[J][h] = sv;
+          carry[J][h] = Pn[h];
+          // moments as residuals against the wave's first slot (see accumulate)
+          Es[h] += sv;
+          if constexpr (J == 0) ref[h] = sv * d.invw;
+          const T r = fma(-d.w, ref[h], sv);
+          F0[h] = fma(d.n0, r, F0[h]);
+          F1[h] = fma(d.n1, r, F1[h]);
+          F2[h] = fma(d.n2, r, F2[h]);
+        }
+      };
+      unroll<0, M>(slot);
+    }
+
+    // ---- the waves' partial sums of the 128 cells
+    *reinterpret_cast<f32x2 *>(&red[q][0][2 * lane]) = f32x2{Es[0], Es[1]};
+    *reinterpret_cast<f32x2 *>(&red[q][1][2 * lane]) = f32x2{F0[0], F0[1]};
+    *reinterpret_cast<f32x2 *>(&red[q][2][2 * lane]) = f32x2{F1[0], F1[1]};
+    *reinterpret_cast<f32x2 *>(&red[q][3][2 * lane]) = f32x2{F2[0], F2[1]};
+    __syncthreads();
+
+    // ---- combine: item r of this lane is moment j of cell cc (j uniform per wave)
+#pragma unroll
+    for (int r = 0; r < RI; ++r) {
+      const int j = r * (NW / 2) + (q >> 1);
+      T v[NW];
+#pragma unroll
+      for (int w = 0; w < NW; ++w) v[w] = red[w][j][cc];
+      const T Sm = tree_sum<T, NW>(v);
+      if (j == 0) {
+        const CoefE<T> ce = coef_E<T>(p.mode, p.lambda_iters, dt, Sm, kat, kst, et);
+        coef[0][cc] = ce.c;
+        coef[1][cc] = ce.alpha;
+        if (valid_c) {
+          if (p.flags & KF_WRITE_EF) Eout[cz + ocell] = ce.En;
+          if (diag) {
+            sE += (double)ce.En;
+            sEs += (double)Sm;
+          }
+        }
+      } else {
+        T Fn, be;
+        coef_F<T>(p.mode, p.lambda_iters, dt, lam, Sm, kat, kst, Fn, be);
+        coef[1 + j][cc] = be;
+        if (valid_c && (p.flags & KF_WRITE_EF)) Fout[(int64_t)(j - 1) * p.ncell + cz + ocell] = Fn;
+      }
+    }
+    // the next plane's medium and first loads go out before the stores
+    load_medium(cz_next, om);
+    if (z + 1 < ze) issue_first(z + 1);
+    __syncthreads();
+
+    // ---- collide and store both cells of every slot
+    const f32x2 c2 = *reinterpret_cast<const f32x2 *>(&coef[0][2 * lane]);
+    const f32x2 a2 = *reinterpret_cast<const f32x2 *>(&coef[1][2 * lane]);
+    f32x2 b0 = {T(0), T(0)}, b1 = {T(0), T(0)}, b2 = {T(0), T(0)};
+    if (!lamzero) {
+      b0 = *reinterpret_cast<const f32x2 *>(&coef[2][2 * lane]);
+      b1 = *reinterpret_cast<const f32x2 *>(&coef[3][2 * lane]);
+      b2 = *reinterpret_cast<const f32x2 *>(&coef[4][2 * lane]);
+    }
+    char *const outz = reinterpret_cast<char *>(Iout) + cz * SZ;
+    const uint32_t ost = opaque_lane(o0);
+    const PairColl *__restrict__ tbc = ctab + opaque(q * M);
+    uint32_t g0 = 0u, g1 = 0u;
+    if (sizeof(S) == 2 && stoch) {
+      const uint32_t cell0 = (uint32_t)(cz + x + nx * y);
+      g0 = cell_hash(cell0 ^ p.seed);
+      g1 = cell_hash((cell0 + 1u) ^ p.seed);
+    }
+    if (valid) {
+#pragma unroll
+      for (int jj = 0; jj < M; ++jj) {
+        const PairColl &d = tbc[jj];
+        if (d.inv_scale != T(0)) {   // a direction (padding slots carry 0)
+          T o0v = collide_pair(d, c2.x, a2.x, b0.x, b1.x, b2.x, Is[jj][0], lamzero);
+          T o1v = collide_pair(d, c2.y, a2.y, b0.y, b1.y, b2.y, Is[jj][1], lamzero);
+          if constexpr (sizeof(S) == 2) {
+            o0v *= d.inv_scale;
+            o1v *= d.inv_scale;
+          }
+          IO::st(outz + d.plane_off, ost, o0v, o1v, g0 ^ d.rnd, g1 ^ d.rnd, stoch);
+        }
+      }
+    }
+  }
+
+  if (diag) {
+    double v[kStepPartials];
+#pragma unroll
+    for (int k = 0; k < kStepPartials; ++k) v[k] = 0.0;
+    v[0] = sE;
+    v[1] = sEs;
+    block_sums<kStepPartials, NW>(v, partials + (int64_t)blockIdx.x * kStepPartials);
+  }
+}
+
+// Interior tiles of 128 cells, in the XCD-aware block order of the main kernel.
+template <typename S, int NB>
+__global__ void __launch_bounds__(64 * waves_for(NB), waves_per_simd<S>(NB))
+step_kernel_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__ ka,
+                 const float *__restrict__ ks, const float *__restrict__ eta,
+                 const PairTab *__restrict__ tab, const PairColl *__restrict__ ctab,
+                 const KParams p, float *__restrict__ Eout, float *__restrict__ Fout,
+                 double *__restrict__ partials) {
+  const int t = xcd_tile(blockIdx.x, p.nblocks);
+  const int tix = t % p.ntx;
+  const int r = t / p.ntx;
+  const int y = p.main_ty0 + r % p.main_nty;
+  const int tzr = p.main_zr0 + r / p.main_nty;
+  const int zb = tzr * p.zlen;
+  march_pair<S, NB>(Iin, Iout, ka, ks, eta, tab, ctab, p, Eout, Fout, partials, 128 * tix, y,
+                    zb, min(p.nz, zb + p.zlen));
+}
+
+}  // namespace lbrt

@@ -70,6 +70,11 @@ StepLauncher step_launcher(int storage, int bucket_index, bool moving) {
   return nullptr;
 }
 
+bool pair_available(int storage, int nb, bool moving) {
+  return !moving && (storage == LBRT_BF16 || storage == LBRT_FP16) &&
+         (nb == 56 || nb == 112);
+}
+
 BatchLauncher batch_f32_16_static();
 BatchLauncher batch_f32_32_static();
 BatchLauncher batch_f32_56_static();

@@ -93,6 +93,51 @@ template <> struct StoreTraits<f16_t> {
   }
 };
 
+// ---------------------------------------------------------------------------
+// Stochastic rounding of 16-bit storage.  Round-to-nearest loses any
+// per-step change smaller than half a unit in the last place: with 8 (BF16)
+// or 11 (FP16) significant bits, a population that an absorbing cell dims by
+// less than that per step keeps its value for ever.  Rounding up with the
+// probability of the dropped fraction is exact in expectation.  gfx950
+// converts with stochastic rounding in one instruction (v_cvt_sr_*_f32; it
+// adds the high 16 (BF16) or 13 (FP16) of 32 random bits to the dropped
+// part), driven by 32 random bits per element: a hash of the cell's index
+// combined with the step's seed, then the exclusive or with a random constant
+// of the direction's plane.  The seed goes through the hash: with a plain
+// exclusive or, bits that two steps' seeds share would be equal for every
+// element in both steps, which correlates an element's rounding with its own
+// previous one and biases the run (measured: 6e-4 after 200 steps of slow
+// decay).  Every kernel path draws the same bits for an element, so they
+// keep giving the same values.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t cell_hash(uint32_t c) {
+  c ^= c >> 16;
+  c *= 0x7feb352du;
+  c ^= c >> 15;
+  c *= 0x846ca68bu;
+  c ^= c >> 16;
+  return c;
+}
+
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+
+template <typename S> __device__ __forceinline__ uint16_t to16_sr(float v, uint32_t r);
+template <> __device__ __forceinline__ uint16_t to16_sr<bf16_t>(float v, uint32_t r) {
+  const s16x2 h = __builtin_amdgcn_cvt_sr_bf16_f32(s16x2{0, 0}, v, r, false);
+  return (uint16_t)h.x;
+}
+template <> __device__ __forceinline__ uint16_t to16_sr<f16_t>(float v, uint32_t r) {
+  const f16x2 h = __builtin_amdgcn_cvt_sr_f16_f32(f16x2{0, 0}, v, r, false);
+  return __builtin_bit_cast(uint16_t, h.x);
+}
+
+// Store of a 16-bit population with stochastic rounding (random bits r).
+template <typename S>
+__device__ __forceinline__ void sto_sr(char *base, uint32_t byte_off, float v, uint32_t r) {
+  __builtin_nontemporal_store(to16_sr<S>(v, r), reinterpret_cast<uint16_t *>(base + byte_off));
+}
+
 // Load at a wave-uniform base plus a lane's byte offset.
 template <typename S>
 __device__ __forceinline__ typename StoreTraits<S>::T ldo(const S *base, uint32_t byte_off) {
@@ -447,8 +492,83 @@ __device__ __forceinline__ void accumulate(Acc<T> &m, const DirTab<T> *__restric
 }
 
 // ---------------------------------------------------------------------------
+// Collision of a static fluid, per cell.  Every mode becomes
+//   I_i = c I*_i + w_i (alpha + n_i . beta),
+// and the new moments E', F' follow.  The E part (c, alpha, E') needs only E*
+// and the F part (beta_a, F'_a) only F*_a, so the pair kernels compute them
+// in different waves; both kernels call these functions, with explicit fused
+// multiply-adds, so that they give the same bits for a cell.
+//   implicit  eq. (rte_implicit) solved exactly: E' = (E* + dt eta)/(1 + dt ka),
+//             F' = F*/(1 + dt (k0 + ka) - dt k0 lam/3);
+//   explicit  eq. (collision-step) with I^eq and S of eq. (source-and-equil);
+//   Lambda    `iters` cycles of the Lambda iteration: (E, F) <- moments of the
+//             decoupled solution, which the rule's identities reduce to a
+//             scalar recursion per cell.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct CoefE {
+  T c, alpha, En;
+};
+
+template <typename T>
+__device__ __forceinline__ CoefE<T> coef_E(int mode, int iters, T dt, T Es, T ka, T ks, T et) {
+  CoefE<T> r;
+  if (mode == LBRT_COLL_EXPLICIT) {
+    r.c = fma(-dt, ks + ka, T(1));
+    r.alpha = dt * fma(ks, Es, et);
+    r.En = fma(r.c, Es, r.alpha);
+  } else if (mode == LBRT_COLL_LAMBDA) {
+    r.c = div_fast(T(1), fma(dt, ks + ka, T(1)));
+    T Ek = Es;
+    for (int it = 1; it < iters; ++it) Ek = r.c * fma(dt, fma(ks, Ek, et), Es);
+    r.alpha = r.c * dt * fma(ks, Ek, et);
+    r.En = fma(r.c, Es, r.alpha);
+  } else {
+    r.c = div_fast(T(1), fma(dt, ks + ka, T(1)));
+    r.En = div_fast(fma(dt, et, Es), fma(dt, ka, T(1)));
+    r.alpha = r.c * dt * fma(ks, r.En, et);
+  }
+  return r;
+}
+
+// One flux component: F'_a and beta_a (beta is 0 when lam == 0).
+template <typename T>
+__device__ __forceinline__ void coef_F(int mode, int iters, T dt, T lam, T F, T ka, T ks, T &Fn,
+                                       T &beta) {
+  const T third = T(1) / T(3);
+  if (mode == LBRT_COLL_EXPLICIT) {
+    const T c = fma(-dt, ks + ka, T(1));
+    beta = dt * ks * lam * F;
+    Fn = fma(beta, third, c * F);
+  } else if (mode == LBRT_COLL_LAMBDA) {
+    const T c = div_fast(T(1), fma(dt, ks + ka, T(1)));
+    const T h = dt * ks * lam * third;
+    T G = F;
+    for (int it = 1; it < iters; ++it) G = c * fma(h, G, F);
+    beta = c * dt * ks * lam * G;
+    Fn = fma(beta, third, c * F);
+  } else {
+    const T den = fma(dt, ks + ka, T(1));
+    const T c = div_fast(T(1), den);
+    const T gF = div_fast(T(1), fma(-(dt * ks * lam), third, den));
+    Fn = F * gF;
+    beta = c * dt * ks * lam * Fn;
+  }
+}
+
+// New population of one direction of a cell from its streamed value.
+template <typename T>
+__device__ __forceinline__ T collide_one(const DirTab<T> &d, T c, T alpha, T b0, T b1, T b2, T Is,
+                                         bool lamzero) {
+  if (lamzero) return fma(c, Is, d.w * alpha);
+  const T nb = fma(d.n[2], b2, fma(d.n[1], b1, fma(d.n[0], b0, alpha)));
+  return fma(c, Is, d.w * nb);
+}
+
+// ---------------------------------------------------------------------------
 // The fused step.  NB direction slots (a multiple of 8, padded with null
-// directions); wave q owns slots [q NB/4, (q+1) NB/4).
+// directions); wave q owns slots [q NB/NW, (q+1) NB/NW).  The tile is 64
+// cells, 2^txlog wide in x; cells outside [0, xe) x [0, ye) are inactive.
 // ---------------------------------------------------------------------------
 template <typename S, int NB, bool MOVING, bool MAIN, int NW = waves_for(NB)>
 __device__ __forceinline__ void
@@ -457,7 +577,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
       const DirTab<typename StoreTraits<S>::T> *__restrict__ tab, const KParams &p,
       const InflowArgs *__restrict__ inflow, typename StoreTraits<S>::T *__restrict__ Eout,
       typename StoreTraits<S>::T *__restrict__ Fout, double *__restrict__ partials, int x0,
-      int y0, int zb, int ze) {
+      int y0, int zb, int ze, int txlog, int xe, int ye) {
   using Tr = StoreTraits<S>;
   using T = typename Tr::T;
   constexpr int SZ = (int)sizeof(S);
@@ -471,9 +591,10 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
   const int lane = threadIdx.x & 63;
   const int perx = p.periodic[0], pery = p.periodic[1], perz = p.periodic[2];
 
-  const int x = x0 + (lane & (p.tx - 1));
-  const int y = y0 + (lane >> p.txlog);
-  const bool valid = x < nx && y < ny;
+  const int tx = 1 << txlog, ty = kTileCells >> txlog;
+  const int x = x0 + (lane & (tx - 1));
+  const int y = y0 + (lane >> txlog);
+  const bool valid = x < xe && y < ye;
   // Byte offsets in a plane: the lane's cell, and its x-shifted tap x - sx
   // for sx > 0 / sx < 0; on a face lane the wrapped cell (periodic) or the
   // lane's own cell (a vacuum/inflow ghost: zeroed).  All offsets stay inside
@@ -498,8 +619,8 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
   const T xop = hix ? T(1) : T(0), xom = lox ? T(1) : T(0);
 
   const bool diag = (p.flags & KF_DIAG) != 0;
-  const bool xface_tile = !perx && (x0 == 0 || x0 + p.tx >= nx);
-  const bool face_tile = xface_tile || (!pery && (y0 == 0 || y0 + p.ty >= ny));
+  const bool xface_tile = !perx && (x0 == 0 || x0 + tx >= nx);
+  const bool face_tile = xface_tile || (!pery && (y0 == 0 || y0 + ty >= ny));
 
   // This wave's slots.  Every plane re-reads them (scalar cache hits)
   // through an opaque copy of the pointer: hoisted out of the z loop, they
@@ -569,7 +690,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
   // ghost pointer and shift sign from memory on every plane.
   uint32_t xgmask = 0u;
   if ((p.flags & KF_XGHOSTS) && xface_tile) {
-    const bool tlo = x0 == 0, thi = x0 + p.tx >= nx;
+    const bool tlo = x0 == 0, thi = x0 + tx >= nx;
     auto scan = [&]<int J>() {
       const DirTab<T> &d = tab[q * M + J];
       if (inflow->ghost[q * M + J][0] != nullptr && ((d.s[0] > 0 && tlo) || (d.s[0] < 0 && thi)))
@@ -820,55 +941,34 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
     const DirTab<T> *__restrict__ tbc = tab + opaque(q * M);
     T En = T(0), Fn0 = T(0), Fn1 = T(0), Fn2 = T(0);
     if constexpr (!MOVING) {
-      const T F0 = S0, F1 = S1, F2 = S2;
-      // Collision: every mode becomes I_i = c I*_i + w_i (alpha + n_i . beta).
       const T lam = (T)p.lam;
-      const T third = T(1) / T(3);
-      T c, alpha, be0, be1, be2;
-      if (p.mode == LBRT_COLL_EXPLICIT) {
-        // eq. (collision-step) with I^eq and S of eq. (source-and-equil)
-        c = T(1) - dt * (kst + kat);
-        alpha = dt * (kst * EsT + et);
-        const T g = dt * kst * lam;
-        be0 = g * F0; be1 = g * F1; be2 = g * F2;
-        En = c * EsT + alpha;
-        Fn0 = fma(be0, third, c * F0); Fn1 = fma(be1, third, c * F1); Fn2 = fma(be2, third, c * F2);
-      } else if (p.mode == LBRT_COLL_LAMBDA) {
-        // Lambda iteration: (E, F) <- moments of the decoupled solution,
-        // which the rule's identities reduce to a scalar recursion per cell.
-        c = div_fast(T(1), T(1) + dt * (kst + kat));
-        T Ek = EsT, G0 = F0, G1 = F1, G2 = F2;
-        const T h = dt * kst * lam * third;
-        for (int it = 1; it < p.lambda_iters; ++it) {
-          Ek = c * (EsT + dt * (kst * Ek + et));
-          G0 = c * (F0 + h * G0); G1 = c * (F1 + h * G1); G2 = c * (F2 + h * G2);
-        }
-        alpha = c * dt * (kst * Ek + et);
-        const T g = c * dt * kst * lam;
-        be0 = g * G0; be1 = g * G1; be2 = g * G2;
-        En = c * EsT + alpha;
-        Fn0 = fma(be0, third, c * F0); Fn1 = fma(be1, third, c * F1); Fn2 = fma(be2, third, c * F2);
-      } else {
-        // eq. (rte_implicit) solved exactly: the moment equations decouple to
-        // E = (E* + dt eta)/(1 + dt ka), F = F*/(1 + dt(k0 + ka) - dt k0 lam/3).
-        const T den = T(1) + dt * (kst + kat);
-        c = div_fast(T(1), den);
-        En = div_fast(EsT + dt * et, T(1) + dt * kat);
-        const T gF = div_fast(T(1), den - dt * kst * lam * third);
-        Fn0 = F0 * gF; Fn1 = F1 * gF; Fn2 = F2 * gF;
-        alpha = c * dt * (kst * En + et);
-        const T g = c * dt * kst * lam;
-        be0 = g * Fn0; be1 = g * Fn1; be2 = g * Fn2;
-      }
+      const CoefE<T> ce = coef_E<T>(p.mode, p.lambda_iters, dt, EsT, kat, kst, et);
+      T be0, be1, be2;
+      coef_F<T>(p.mode, p.lambda_iters, dt, lam, S0, kat, kst, Fn0, be0);
+      coef_F<T>(p.mode, p.lambda_iters, dt, lam, S1, kat, kst, Fn1, be1);
+      coef_F<T>(p.mode, p.lambda_iters, dt, lam, S2, kat, kst, Fn2, be2);
+      En = ce.En;
+      const T c = ce.c, alpha = ce.alpha;
       load_medium(cz_next, om);
       issue_next();
       if (valid) {
-        if (p.flags & KF_LAMZERO) {
+        const bool lz = (p.flags & KF_LAMZERO) != 0;
+        if (Tr::kReduced && (p.flags & KF_STOCH)) {
+          const uint32_t gr = cell_hash((uint32_t)(cz + ocell) ^ p.seed);
+#pragma unroll
+          for (int j = 0; j < M; ++j) {
+            const DirTab<T> &d = tbc[j];
+            if (d.active)
+              sto_sr<S>(outz + d.plane_off, ost,
+                        collide_one(d, c, alpha, be0, be1, be2, Is[j], lz) * d.inv_scale,
+                        gr ^ d.rnd);
+          }
+        } else if (lz) {
 #pragma unroll
           for (int j = 0; j < M; ++j) {
             const DirTab<T> &d = tbc[j];
             if (d.active) {
-              T o = fma(c, Is[j], d.w * alpha);
+              T o = collide_one(d, c, alpha, be0, be1, be2, Is[j], true);
               if (Tr::kReduced) o *= d.inv_scale;
               sto<S>(outz + d.plane_off, ost, o);
             }
@@ -878,8 +978,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
           for (int j = 0; j < M; ++j) {
             const DirTab<T> &d = tbc[j];
             if (d.active) {
-              const T nb = alpha + d.n[0] * be0 + d.n[1] * be1 + d.n[2] * be2;
-              T o = fma(c, Is[j], d.w * nb);
+              T o = collide_one(d, c, alpha, be0, be1, be2, Is[j], false);
               if (Tr::kReduced) o *= d.inv_scale;
               sto<S>(outz + d.plane_off, ost, o);
             }
@@ -900,6 +999,8 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
       const T gam = div_fast(dt * (et + kst * J), W * W * W);
       issue_next();
       T e = T(0), f0 = T(0), f1 = T(0), f2 = T(0), ref = T(0);
+      const bool sr = Tr::kReduced && (p.flags & KF_STOCH);
+      const uint32_t gr = sr ? cell_hash((uint32_t)(cz + ocell) ^ p.seed) : 0u;
       if (valid) {
 #pragma unroll
         for (int j = 0; j < M; ++j) {
@@ -916,7 +1017,12 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
             f0 = fma(d.n[0], r, f0);
             f1 = fma(d.n[1], r, f1);
             f2 = fma(d.n[2], r, f2);
-            sto<S>(outz + d.plane_off, ost, Tr::kReduced ? o * d.inv_scale : o);
+            if constexpr (Tr::kReduced) {
+              if (sr) sto_sr<S>(outz + d.plane_off, ost, o * d.inv_scale, gr ^ d.rnd);
+              else sto<S>(outz + d.plane_off, ost, o * d.inv_scale);
+            } else {
+              sto<S>(outz + d.plane_off, ost, o);
+            }
           }
         }
       }
@@ -995,7 +1101,8 @@ step_kernel_main(const S *__restrict__ Iin, S *__restrict__ Iout, const float *_
   const int tzr = p.main_zr0 + r / p.main_nty;
   const int zb = tzr * p.zlen;
   march<S, NB, MOVING, true>(Iin, Iout, ka, ks, eta, vel, tab, p, inflow, Eout, Fout, partials,
-                             tix * p.tx, tiy * p.ty, zb, min(p.nz, zb + p.zlen));
+                             tix * p.tx, tiy * p.ty, zb, min(p.nz, zb + p.zlen), p.txlog, p.nx,
+                             p.ny);
 }
 
 // The general kernel: every other tile (y-face rows, ragged tiles, z ranges
@@ -1010,9 +1117,10 @@ step_kernel_general(const S *__restrict__ Iin, S *__restrict__ Iout,
                     const InflowArgs *__restrict__ inflow,
                     typename StoreTraits<S>::T *__restrict__ Eout,
                     typename StoreTraits<S>::T *__restrict__ Fout, double *__restrict__ partials) {
-  const int4 w = p.general_list[blockIdx.x];
+  const GenTile &g = p.general_list[blockIdx.x];
   march<S, NB, MOVING, false>(Iin, Iout, ka, ks, eta, vel, tab, p, inflow, Eout, Fout,
-                              partials + (int64_t)p.nblocks * kStepPartials, w.x, w.y, w.z, w.w);
+                              partials + (int64_t)p.nblocks * kStepPartials, g.x0, g.y0, g.zb,
+                              g.ze, g.txlog, g.xe, g.ye);
 }
 
 // ---------------------------------------------------------------------------
@@ -1067,6 +1175,12 @@ zface_kernel(const S *__restrict__ I, const DirTab<typename StoreTraits<S>::T> *
       v, partials + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * kStepPartials);
 }
 
+}  // namespace lbrt
+
+#include "lbrt_pair_kernel.h"
+
+namespace lbrt {
+
 template <typename S, int NB, bool MOVING>
 hipError_t launch_step(const void *Iin, void *Iout, const float *ka, const float *ks,
                        const float *eta, const float *vel, const void *tab, const KParams &p,
@@ -1080,6 +1194,16 @@ hipError_t launch_step(const void *Iin, void *Iout, const float *ka, const float
                        s, static_cast<const S *>(Iin), static_cast<S *>(Iout), ka, ks, eta, vel,
                        static_cast<const DirTab<T> *>(tab), p, inflow, static_cast<T *>(E),
                        static_cast<T *>(F), partials);
+  if constexpr (pair_kernel_exists<S, NB, MOVING>()) {
+    if (p.pair) {
+      if (p.nblocks > 0)
+        hipLaunchKernelGGL((step_kernel_pair<S, NB>), dim3(p.nblocks), dim3(64 * waves_for(NB)),
+                           0, s, static_cast<const S *>(Iin), static_cast<S *>(Iout), ka, ks, eta,
+                           p.pair_tab, p.pair_coll, p, static_cast<float *>(E),
+                           static_cast<float *>(F), partials);
+      return hipGetLastError();
+    }
+  }
   if (p.nblocks > 0)
     hipLaunchKernelGGL((step_kernel_main<S, NB, MOVING>), dim3(p.nblocks),
                        dim3(64 * waves_for(NB)), 0, s,

@@ -52,13 +52,16 @@ def upload_fields(prob):
 
 
 def run_problem(prob, storage=None, steps=None, I0=None, want_diag=True, collision=None,
-                tile=None, zlen=None, zlen_general=None, fp64_flux_term=None):
+                tile=None, zlen=None, zlen_general=None, fp64_flux_term=None, pair=None,
+                rounding=None):
     """Run ``steps`` GPU steps; returns dict with float64 numpy I (decoded),
     E, F, diag and the oracle's starting state ``I0_eff``.  ``tile``
     ("TXxTY"), ``zlen`` and ``zlen_general`` override the context's tiling
     (they change which cells take which kernel path, never the results);
     ``fp64_flux_term`` keeps the FP64 reference term of the flux sums even
-    where it is exactly 0 (the results must not change either)."""
+    where it is exactly 0 (the results must not change either); ``pair=False``
+    runs the interior on the one-cell-per-lane kernel instead of the pair
+    kernel (same bits); ``rounding`` picks the 16-bit rounding mode."""
     import os
     torch = torch_mod()
     L = lib()
@@ -67,9 +70,12 @@ def run_problem(prob, storage=None, steps=None, I0=None, want_diag=True, collisi
     kw = {}
     if collision is not None:
         kw["collision"] = collision
+    if rounding is not None:
+        kw["rounding"] = rounding
     desc = L.Desc.from_problem(prob, storage=storage, **kw)
     env = {"LBRT_TILE": tile, "LBRT_ZLEN": zlen, "LBRT_ZLEN_GENERAL": zlen_general,
-           "LBRT_FP64_FLUX_TERM": 1 if fp64_flux_term else None}
+           "LBRT_FP64_FLUX_TERM": 1 if fp64_flux_term else None,
+           "LBRT_PAIR": None if pair is None else (1 if pair else 0)}
     old = {k: os.environ.get(k) for k in env}
     for k, v in env.items():
         if v is not None:

@@ -10,10 +10,11 @@ as a global relative L2 error and element by element.
 * BF16/FP16 storage (E and F only, from the FP32 collision): 2e-3 relative
   L2, and element by element |dE|, |dF| <= 2 k u max E after k steps, u the
   unit roundoff of the 16-bit format (2^-8 BF16, 2^-11 FP16): each step
-  rounds every stored population once (relative error <= u) and the pull
-  and the implicit collision are averages with nonnegative weights, so a
-  cell's accumulated error stays below k u times the energy scale; the
-  factor 2 covers the FP32 arithmetic around it.
+  rounds every stored population once, stochastically, to one of its two
+  neighbouring 16-bit values (relative error below one unit in the last
+  place, 2u), and the pull and the implicit collision are averages with
+  nonnegative weights, so a cell's accumulated error stays below 2 k u times
+  the energy scale (the FP32 arithmetic around it adds far less).
 """
 import numpy as np
 import pytest
@@ -241,19 +242,23 @@ def test_exact_shift_is_bit_exact():
         assert np.array_equal(res["I"][i], ref)
 
 
+@pytest.mark.parametrize("storage", ["fp32", "bf16"])
 @pytest.mark.parametrize("bc,planes", [
     ((wl.BC_PERIODIC, wl.BC_PERIODIC) + (wl.BC_OUTFLOW,) * 4, 0),
     ((wl.BC_INFLOW, wl.BC_INFLOW, wl.BC_INFLOW, wl.BC_OUTFLOW, wl.BC_PERIODIC, wl.BC_PERIODIC), 6),
 ])
-def test_tile_shapes_are_bit_identical(bc, planes):
+def test_tile_shapes_are_bit_identical(bc, planes, storage):
     """Tile shape and z-range lengths change which cells take which kernel
-    (main or general) and where the z-march starts; results must not move."""
+    (main, pair or general) and where the z-march starts; results must not
+    move.  BF16 runs the interior on the pair kernel, with the same
+    stochastic rounding bits for a cell whichever kernel stores it."""
+    st = {"fp32": L().LBRT_FP32, "bf16": L().LBRT_BF16}[storage]
     p = wl.random_problem(41, shape=(12, 16, 140), npoints=50, steps=2, bc=bc,
                           inflow_planes=planes)
-    ref = gh.run_problem(p, storage=L().LBRT_FP32, tile="64x1")
+    ref = gh.run_problem(p, storage=st, tile="64x1")
     for tile, zlen, zg in (("32x2", None, None), ("16x4", None, None), ("8x8", None, None),
                            ("64x1", 1, 1), ("64x1", 5, 3), ("64x1", 12, 12), ("32x2", 7, 2)):
-        got = gh.run_problem(p, storage=L().LBRT_FP32, tile=tile, zlen=zlen, zlen_general=zg)
+        got = gh.run_problem(p, storage=st, tile=tile, zlen=zlen, zlen_general=zg)
         assert np.array_equal(got["I"], ref["I"]), (tile, zlen, zg)
         assert np.array_equal(got["E"], ref["E"]), (tile, zlen, zg)
 
@@ -273,3 +278,88 @@ def test_sphere_fp64_full_length():
     I = orc.run(p)
     E, F = orc.moments(I, p.dirs)
     check(res, I, E, F, 1e-12)
+
+
+@pytest.mark.parametrize("storage,npoints,shape,bc,planes,coll,lam", [
+    ("fp16", 110, (12, 16, 140), (wl.BC_INFLOW, wl.BC_OUTFLOW, wl.BC_INFLOW, wl.BC_OUTFLOW,
+                                  wl.BC_INFLOW, wl.BC_OUTFLOW), 6, wl.COLL_IMPLICIT, 0.0),
+    ("bf16", 50, (9, 11, 70), (wl.BC_PERIODIC,) * 6, 0, wl.COLL_IMPLICIT, 0.3),
+    ("fp16", 110, (7, 9, 266), (wl.BC_OUTFLOW,) * 6, 0, wl.COLL_EXPLICIT, -0.25),
+    ("bf16", 50, (8, 10, 136), (wl.BC_PERIODIC, wl.BC_PERIODIC, wl.BC_OUTFLOW, wl.BC_INFLOW,
+                                wl.BC_PERIODIC, wl.BC_PERIODIC), 3, wl.COLL_LAMBDA, 0.5),
+    ("bf16", 110, (12, 16, 140), (wl.BC_INFLOW, wl.BC_OUTFLOW, wl.BC_INFLOW, wl.BC_OUTFLOW,
+                                  wl.BC_OUTFLOW, wl.BC_OUTFLOW), 4, wl.COLL_IMPLICIT, 0.0),
+    ("fp16", 50, (9, 11, 70), (wl.BC_PERIODIC,) * 6, 0, wl.COLL_IMPLICIT, 0.0),
+    ("bf16", 50, (10, 12, 134), (wl.BC_OUTFLOW,) * 6, 0, wl.COLL_IMPLICIT, 0.4),
+])
+def test_pair_kernel_equals_main_kernel(storage, npoints, shape, bc, planes, coll, lam):
+    """The interior on the two-cells-per-lane kernel (x in [2, nx - 2), the
+    face columns on the checked path) against the one-cell-per-lane main
+    kernel: the same populations, E and F bit for bit (with the same
+    stochastic rounding bits).  The diagnostics are sums in a
+    different grouping: the energy sums (FP64 per lane) to 1e-12, the face
+    fluxes (FP32 per lane over a block's z range, then FP64) to 1e-6."""
+    st = {"bf16": L().LBRT_BF16, "fp16": L().LBRT_FP16}[storage]
+    p = wl.random_problem(91, shape=shape, npoints=npoints, bc=bc, inflow_planes=planes,
+                          collision=coll, lam=lam, steps=3,
+                          kappa_range=(-2.0, 2.0) if coll == wl.COLL_IMPLICIT else (-2.0, 0.0))
+    print(f"pair vs main: {storage} {shape} x {npoints}", flush=True)
+    a = gh.run_problem(p, storage=st, pair=True)
+    b = gh.run_problem(p, storage=st, pair=False)
+    torch = gh.torch_mod()
+    torch.cuda.synchronize()
+    assert torch.equal(a["raw"], b["raw"])
+    assert np.array_equal(a["E"], b["E"]) and np.array_equal(a["F"], b["F"])
+    scale = a["I0_eff"].sum()
+    d = np.abs(a["diag"] - b["diag"])
+    assert max(d[0], d[8]) <= 1e-12 * scale
+    assert np.max(d[1:8]) <= 1e-6 * scale
+
+
+def test_pair_kernel_against_oracle_ragged():
+    """The pair kernel (FP16) on a box whose interior is not a whole number
+    of 128-cell tiles, against the FP64 oracle with the 16-bit bounds of the
+    module doc."""
+    p = wl.random_problem(93, shape=(9, 10, 174), npoints=110, steps=2,
+                          bc=(wl.BC_INFLOW, wl.BC_OUTFLOW, wl.BC_OUTFLOW, wl.BC_INFLOW,
+                              wl.BC_OUTFLOW, wl.BC_OUTFLOW), inflow_planes=3)
+    res = gh.run_problem(p, storage=L().LBRT_FP16, pair=True)
+    I, E, F, _ = oracle_run(p, res["I0_eff"], p.steps)
+    check(res, I, E, F, None, tol_ef=2e-3, steps=p.steps, unit_roundoff=2.0 ** -11)
+
+
+@pytest.mark.parametrize("storage", ["bf16", "fp16"])
+def test_stochastic_rounding_follows_slow_decay(storage):
+    """A uniform isotropic field in a periodic box with weak absorption
+    (dt kappa_a = 1e-4, below half a unit in the last place of both formats
+    at the stored values, 1.0): each step multiplies every population by
+    c = 1 / (1 + dt kappa_a).  With round-to-nearest the stored values never
+    change; with stochastic rounding the mean over cells follows c^n, within
+    a few standard errors of the per-element rounding noise."""
+    Lb = L()
+    st = {"bf16": Lb.LBRT_BF16, "fp16": Lb.LBRT_FP16}[storage]
+    u = {"bf16": 2.0 ** -8, "fp16": 2.0 ** -11}[storage]
+    p = wl.random_problem(95, shape=(16, 16, 64), npoints=26, steps=200,
+                          bc=(wl.BC_PERIODIC,) * 6)
+    p.kappa_a[:] = 2e-4
+    p.kappa_s[:] = 0.0
+    p.eta[:] = 0.0
+    p.I0 = np.broadcast_to(p.weights[:, None, None, None], (p.ndir,) + p.shape).copy()
+    c = 1.0 / (1.0 + p.dt * np.float64(np.float32(2e-4)))
+    exact = c ** p.steps * p.weights.sum()
+    near = gh.run_problem(p, storage=st, rounding=Lb.LBRT_ROUND_NEAREST, want_diag=False)
+    sto = gh.run_problem(p, storage=st, rounding=Lb.LBRT_ROUND_STOCHASTIC, want_diag=False)
+    # the stored populations (decoded); E is formed before the rounding
+    m_near = near["I"].sum(axis=0).mean()
+    m_sto = sto["I"].sum(axis=0).mean()
+    # each step adds to each stored value a rounding error of zero mean and
+    # variance below (ulp / 2)^2 = u^2 (relative); the sum over the box is
+    # conserved by the periodic pull, so the mean's error has a standard
+    # deviation below u sqrt(steps / (ncell ndir))
+    sigma = u * np.sqrt(p.steps / (p.ncell * p.ndir))
+    print(f"{storage}: exact {exact:.6f}  nearest {m_near:.6f}  stochastic {m_sto:.6f} "
+          f"(sigma {sigma:.1e})", flush=True)
+    # round-to-nearest: every stored value stays at its start (the sum of the
+    # FP32 weights); stochastic: the exact decay within the noise
+    assert abs(m_near - p.weights.sum()) < 1e-6
+    assert abs(m_sto - exact) < 5 * sigma

@@ -5,7 +5,18 @@ FP32, BF16 and FP16 population storage, against the FP64 oracle's moments
 only the oracle).
 
 Errors are reported for E and for F as global relative L2 and as
-max |got - ref| / max |ref|.  FP32 storage: 1e-5, both ways.
+max |got - ref| / max |ref|.  Bounds:
+
+* FP32 storage: 1e-5, both ways.
+* FP16 storage (unit roundoff u = 2^-11): 2e-3 relative L2.
+* BF16 storage (u = 2^-8 = 3.9e-3): 2u = 7.8e-3 relative L2.  In the beam
+  cells one direction carries nearly all of E, so E's relative error there is
+  that population's, and each store rounds it with a relative error of up
+  to u (zero mean, about u / sqrt(3) rms, with stochastic rounding): no
+  8-bit significand gets a beam's E within 2e-3 of the exact one.  The
+  bilinear pull averages the errors of neighbouring cells, which keeps the
+  accumulated error near u (measured: 4.6e-3) rather than growing with the
+  number of steps.
 """
 import os
 
@@ -35,6 +46,8 @@ def _errors(E, F, ref):
 
 @pytest.mark.parametrize("storage,tol_l2,tol_max", [
     ("fp32", 1e-5, 1e-5),
+    ("fp16", 2e-3, None),
+    ("bf16", 2.0 ** -7, None),
 ])
 def test_beams64_500_steps_against_oracle(storage, tol_l2, tol_max):
     L = gh.lib()
