@@ -37,7 +37,12 @@ Readings of the paper that this oracle fixes (the paper is silent there):
   with a prescribed ghost plane for that direction, it takes that ghost
   value; otherwise it is vacuum (0) — this covers outflow faces and
   edge/corner ghosts;
-* the Lambda iteration starts from the moments of the streamed populations.
+* the Lambda iteration starts from the moments of the streamed populations;
+* the sources of the coupling list use k_s = k_0 - k_1 / 3 as that list
+  defines it (eq. rte_gray's momentum sink would be k_0 - k_1; the two agree
+  for isotropic scattering, lam = 0), and H_0 is the time component of H
+  orthogonal to the fluid four-velocity, H_0 = v^j H_j, the sign with which
+  S_0 equals the energy the collision takes from the radiation.
 """
 from __future__ import annotations
 
@@ -338,6 +343,70 @@ def fluid_frame_J(E, F, P, v):
         for b in range(3):
             Pvv += P[a, b] * v[a] * v[b]
     return W2 * (E - 2.0 * Fv + Pvv)
+
+
+def fluid_frame_H(E, F, P, v):
+    """Eq. (J), second line:
+        H_j = W^3 (F^i v_i - E) v_j + W h_ji F^i - W h_ji v_k P^ik,
+        h_ij = W^2 v_i v_j + delta_ij  (projector orthogonal to the fluid),
+    and the time component from the orthogonality of H to the fluid
+    four-velocity (coupling list, item 4), taken as the contravariant one:
+    H^mu u_mu = 0 with u_mu = W (-1, v) (flat metric, signature - + + +,
+    c = 1) gives H_0 = v^j H_j.  With it S_0 of ``four_force`` is the rate at
+    which the collision takes energy from the radiation (the covariant
+    component, -v^j H_j, would flip the sign of the flux term).
+    Returns (H_0, H_x, H_y, H_z) stacked on a leading axis of 4."""
+    v2 = v[0] ** 2 + v[1] ** 2 + v[2] ** 2
+    W = 1.0 / np.sqrt(1.0 - v2)
+    Fv = F[0] * v[0] + F[1] * v[1] + F[2] * v[2]
+    H = np.zeros((4,) + np.shape(E), dtype=np.float64)
+    for j in range(3):
+        Hj = W ** 3 * (Fv - E) * v[j]
+        for i in range(3):
+            h_ji = W ** 2 * v[j] * v[i] + (1.0 if i == j else 0.0)
+            Hj = Hj + W * h_ji * F[i]
+            for k in range(3):
+                Hj = Hj - W * h_ji * v[k] * P[i, k]
+        H[1 + j] = Hj
+    H[0] = v[0] * H[1] + v[1] * H[2] + v[2] * H[3]
+    return H
+
+
+def four_force(J, H, v, kappa_a, kappa_0, eta, lam=0.0):
+    """The radiative sources of the coupling list (Sec. 5, item 4):
+        S_0 = W (ka J - eta) + k H_0,   S_j = W (ka J - eta) v_j + k H_j,
+    fluid-frame ka, eta, with k = ka + k_s and k_s = k_0 - k_1 / 3 as the
+    list defines it; k_1 = lam k_0 / 3 (lam = 3 k_1 / k_0, eq. rte_gray_bgkform),
+    so k = ka + k_0 (1 - lam / 9).  Returns (S_0, S_x, S_y, S_z)."""
+    ka, k0, et = _f64(kappa_a), _f64(kappa_0), _f64(eta)
+    v2 = v[0] ** 2 + v[1] ** 2 + v[2] ** 2
+    W = 1.0 / np.sqrt(1.0 - v2)
+    k = ka + (k0 - (lam * k0 / 3.0) / 3.0)
+    G = W * (ka * J - et)
+    S = np.zeros((4,) + np.shape(J), dtype=np.float64)
+    S[0] = G + k * H[0]
+    for j in range(3):
+        S[1 + j] = G * v[j] + k * H[1 + j]
+    return S
+
+
+def coupling(I, dirs, vel=None, kappa_a=None, kappa_0=None, eta=None, lam=0.0):
+    """What the coupling loop of Sec. 5 takes from a state (items 3 and 4):
+    the lab-frame moments E, F^i, P^ij (eqs. moments_discrete and
+    higher_moments), the fluid-frame J and H_mu (eq. J), and the sources
+    S_0, S_j.  vel None is a fluid at rest.  The sources need the
+    fluid-frame kappa_a, kappa_0 (= kappa_s) and eta; without them S is None.
+    P is returned as its six components xx, xy, xz, yy, yz, zz."""
+    E, F = moments(I, dirs)
+    P = second_moment(I, dirs)
+    v = np.zeros((3,) + E.shape) if vel is None else _f64(vel)
+    J = fluid_frame_J(E, F, P, v)
+    H = fluid_frame_H(E, F, P, v)
+    S = None
+    if kappa_a is not None:
+        S = four_force(J, H, v, kappa_a, kappa_0, eta, lam)
+    P6 = np.stack([P[0, 0], P[0, 1], P[0, 2], P[1, 1], P[1, 2], P[2, 2]])
+    return {"E": E, "F": F, "P": P6, "J": J, "H": H, "S": S}
 
 
 def collide_moving(Istar, dirs, w, kappa_a, kappa_0, eta, vel, dt):

@@ -371,6 +371,176 @@ def test_moving_boosted_equilibrium_is_fixed_point(npoints, tol):
 
 
 # ---------------------------------------------------------------------------
+# Coupling moments and sources (Sec. 3.2 eq. higher_moments; Sec. 5 eq. J and
+# coupling item 4)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("npoints", [14, 50, 110])
+def test_second_moment_identities(npoints):
+    """P is symmetric with trace E (unit directions); an isotropic state
+    I_i = w_i E0 has P = E0 / 3 delta (the rule's isotropy, eq. iso-tensors);
+    a state in one direction has P = n n^T I."""
+    dirs, w = wl.lebedev(npoints)
+    rng = np.random.default_rng(npoints)
+    I = rng.random((npoints, 3, 4, 5))
+    P = orc.second_moment(I, dirs)
+    E, _ = orc.moments(I, dirs)
+    assert np.array_equal(P, P.transpose(1, 0, 2, 3, 4))
+    assert np.max(np.abs(P[0, 0] + P[1, 1] + P[2, 2] - E)) < 1e-13 * E.max()
+    E0 = rng.random((3, 4, 5))
+    Piso = orc.second_moment(w[:, None, None, None] * E0[None], dirs)
+    for a in range(3):
+        for b in range(3):
+            assert np.max(np.abs(Piso[a, b] - (E0 / 3 if a == b else 0.0))) < 1e-14
+    k = npoints // 3
+    one = np.zeros((npoints, 1, 1, 1))
+    one[k] = 2.5
+    np.testing.assert_allclose(orc.second_moment(one, dirs)[:, :, 0, 0, 0],
+                               2.5 * np.outer(dirs[k], dirs[k]), rtol=0, atol=1e-15)
+
+
+def _random_lab_moments(rng, n, vmax):
+    E = rng.random(n) + 1.0
+    F = rng.normal(size=(3, n)) * 0.3
+    A = rng.normal(size=(3, 3, n)) * 0.2
+    P = 0.5 * (A + A.transpose(1, 0, 2)) + np.eye(3)[:, :, None] * (E / 3)
+    v = rng.normal(size=(3, n))
+    v *= rng.uniform(0.0, vmax, n) / np.linalg.norm(v, axis=0)
+    return E, F, P, v
+
+
+def _covariant_JH(E, F, P, v):
+    """J = T^mn u_m u_n and H^m = -h^m_a T^ab u_b, h^m_a = delta + u^m u_a,
+    from the stress tensor T^00 = E, T^0i = F^i, T^ij = P^ij with the
+    Minkowski metric diag(-1, 1, 1, 1)."""
+    n = E.shape[0]
+    T = np.zeros((4, 4, n))
+    T[0, 0] = E
+    T[0, 1:] = F
+    T[1:, 0] = F
+    T[1:, 1:] = P
+    W = 1.0 / np.sqrt(1.0 - (v ** 2).sum(axis=0))
+    u_up = np.concatenate([W[None], W * v])
+    u_dn = u_up * np.array([-1.0, 1.0, 1.0, 1.0])[:, None]
+    J = np.einsum("mnk,mk,nk->k", T, u_dn, u_dn)
+    Tu = np.einsum("abk,bk->ak", T, u_dn)
+    H_up = -(Tu + u_up * np.einsum("ak,ak->k", u_dn, Tu))
+    return J, H_up, u_dn
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_fluid_frame_moments_are_the_covariant_projection(seed):
+    """Eq. (J) written out in E, F, P and v against the tensor projection of
+    the radiation stress tensor onto the fluid four-velocity and its
+    orthogonal complement; H_0 is the contravariant time component."""
+    rng = np.random.default_rng(seed)
+    E, F, P, v = _random_lab_moments(rng, 64, 0.95)
+    J_ref, H_ref, u_dn = _covariant_JH(E, F, P, v)
+    J = orc.fluid_frame_J(E, F, P, v)
+    H = orc.fluid_frame_H(E, F, P, v)
+    scale = np.abs(J_ref).max() + np.abs(H_ref).max()
+    assert np.max(np.abs(J - J_ref)) < 1e-12 * scale
+    assert np.max(np.abs(H - H_ref)) < 1e-12 * scale
+    assert np.max(np.abs(np.einsum("ak,ak->k", H, u_dn))) < 1e-12 * scale
+
+
+def test_boosted_isotropic_radiation():
+    """T^mn = (4/3) J0 u^m u^n + (J0 / 3) g^mn, isotropic radiation of energy
+    density J0 in the fluid frame seen from the lab: eq. (J) gives J = J0 and
+    H = 0, and with eta = kappa_a J0 (radiative equilibrium) both sources
+    vanish for any scattering opacity and lambda."""
+    rng = np.random.default_rng(11)
+    n = 32
+    v = rng.normal(size=(3, n))
+    v *= rng.uniform(0.0, 0.9, n) / np.linalg.norm(v, axis=0)
+    W2 = 1.0 / (1.0 - (v ** 2).sum(axis=0))
+    J0 = rng.uniform(0.5, 2.0, n)
+    E = 4.0 / 3.0 * J0 * W2 - J0 / 3.0
+    F = 4.0 / 3.0 * J0 * W2 * v
+    P = 4.0 / 3.0 * J0 * W2 * v[:, None] * v[None, :] + np.eye(3)[:, :, None] * (J0 / 3.0)
+    J = orc.fluid_frame_J(E, F, P, v)
+    H = orc.fluid_frame_H(E, F, P, v)
+    assert np.max(np.abs(J / J0 - 1.0)) < 1e-12
+    assert np.max(np.abs(H)) < 1e-12 * np.max(J0 * W2)
+    ka = rng.uniform(0.1, 5.0, n)
+    for k0, lam in ((0.0, 0.0), (3.0, 0.0), (2.0, 0.5)):
+        S = orc.four_force(J, H, v, ka, np.full(n, k0), ka * J0, lam)
+        assert np.max(np.abs(S)) < 1e-11 * np.max(ka * J0 * W2)
+
+
+@pytest.mark.parametrize("lam", [0.0, 0.5])
+def test_sources_at_rest(lam):
+    """v = 0: J = E, H_j = F_j, H_0 = 0, S_0 = kappa_a E - eta and
+    S_j = (kappa_a + kappa_0 - kappa_1 / 3) F_j with kappa_1 = lam kappa_0 / 3."""
+    p = _problem(npoints=26, seed=5, lam=lam)
+    rng = np.random.default_rng(3)
+    I = rng.random((p.ndir,) + p.shape)
+    out = orc.coupling(I, p.dirs, None, p.kappa_a, p.kappa_s, p.eta, lam)
+    E, F = out["E"], out["F"]
+    assert np.array_equal(out["J"], E)
+    assert np.max(np.abs(out["H"][1:] - F)) < 1e-15 * E.max()
+    assert np.array_equal(out["H"][0], np.zeros_like(E))
+    ka, k0 = p.kappa_a.astype(np.float64), p.kappa_s.astype(np.float64)
+    np.testing.assert_allclose(out["S"][0], ka * E - p.eta, rtol=1e-14, atol=1e-14 * E.max())
+    k = ka + k0 * (1.0 - lam / 9.0)
+    for j in range(3):
+        np.testing.assert_allclose(out["S"][1 + j], k * F[j], rtol=1e-13,
+                                   atol=1e-14 * E.max() * k.max())
+
+
+def test_sources_are_the_static_collision_exchange():
+    """The implicit collision (eq. rte_implicit, lambda = 0, fluid at rest)
+    evaluates its sink at the new time level, so what it takes from the
+    radiation in one step is dt times the sources of the new state:
+    E - E* = -dt S_0 and F - F* = -dt S_j."""
+    p = _problem(shape=(4, 5, 6), npoints=50, seed=9)
+    rng = np.random.default_rng(4)
+    Istar = rng.random((p.ndir,) + p.shape) * p.weights[:, None, None, None]
+    out = orc.collide_implicit(Istar, p.dirs, p.weights, p.kappa_a, p.kappa_s, p.eta, p.dt)
+    Es, Fs = orc.moments(Istar, p.dirs)
+    c = orc.coupling(out, p.dirs, None, p.kappa_a, p.kappa_s, p.eta)
+    scale = np.abs(c["E"]).max() + p.dt * np.abs(c["S"]).max()
+    assert np.max(np.abs(c["E"] - Es + p.dt * c["S"][0])) < 1e-13 * scale
+    assert np.max(np.abs(c["F"] - Fs + p.dt * c["S"][1:])) < 1e-13 * scale
+
+
+@pytest.mark.parametrize("npoints", [50, 146])
+def test_sources_are_the_moving_collision_exchange(npoints):
+    """The mixed-frame collision of App. B takes from the radiation, in one
+    step, dt times the sources of the new state (the lab-frame four-force),
+    except for the quadrature's error on the fluid-frame emission's lab
+    energy and momentum, <(1 - v.n)^-3> = W^4 and <n (1 - v.n)^-3> = W^4 v:
+        E - E* = -dt S_0 + dt (eta + k0 J) (Q / W^3 - W),
+        F - F* = -dt S_j + dt (eta + k0 J) (Q_j / W^3 - W v_j),
+    Q = sum_i w_i / D_i^3, Q_j = sum_i w_i n_ij / D_i^3 — an identity of the
+    discrete scheme for any rule, which fixes the sign of H_0."""
+    dirs, w = wl.lebedev(npoints)
+    rng = np.random.default_rng(npoints)
+    shape = (2, 3, 4)
+    vel = rng.normal(size=(3,) + shape)
+    vel *= rng.uniform(0.0, 0.6, shape) / np.linalg.norm(vel, axis=0)
+    ka = rng.uniform(0.1, 3.0, shape)
+    k0 = rng.uniform(0.0, 2.0, shape)
+    eta = rng.uniform(0.0, 2.0, shape)
+    dt = 0.5
+    Istar = rng.random((npoints,) + shape) * w[:, None, None, None]
+    out = orc.collide_moving(Istar, dirs, w, ka, k0, eta, vel, dt)
+    Es, Fs = orc.moments(Istar, dirs)
+    c = orc.coupling(out, dirs, vel, ka, k0, eta)
+    W = 1.0 / np.sqrt(1.0 - (vel ** 2).sum(axis=0))
+    Q = np.zeros(shape)
+    Qj = np.zeros((3,) + shape)
+    for i in range(npoints):
+        D = 1.0 - (dirs[i][:, None, None, None] * vel).sum(axis=0)
+        Q += w[i] / D ** 3
+        Qj += w[i] * dirs[i][:, None, None, None] / D ** 3
+    src = dt * (eta + k0 * c["J"])
+    scale = np.abs(c["E"]).max() + dt * np.abs(c["S"]).max() + np.abs(src).max()
+    assert np.max(np.abs(c["E"] - Es + dt * c["S"][0] - src * (Q / W ** 3 - W))) < 1e-13 * scale
+    assert np.max(np.abs(c["F"] - Fs + dt * c["S"][1:] - src * (Qj / W ** 3 - W * vel))) \
+        < 1e-13 * scale
+
+
+# ---------------------------------------------------------------------------
 # Whole steps
 # ---------------------------------------------------------------------------
 def test_diffusion_moments_follow_exact_recursion():
