@@ -250,6 +250,44 @@ def time_collisions(L, torch, n: int, steps: int, warmup: int) -> dict:
     return out
 
 
+def time_coupling(L, torch, prob, reps: int = 10) -> dict:
+    """lbrt_coupling on an FP32 state of the workload with a sheared flow:
+    every output (E, F, P, J, H, S: 19 values per cell) from the 110
+    populations, the velocity and the three opacity fields.  Algorithmic
+    bytes per cell: 110 x 4 + 3 x 4 + 3 x 4 read, 19 x 4 written."""
+    n = prob.ncell
+    ctx = L.lbrt_init(L.Desc.from_problem(prob, storage=L.LBRT_FP32))
+    g = torch.Generator(device="cuda").manual_seed(31)
+    I = torch.rand(prob.ndir * n, generator=g, device="cuda")
+    y = torch.arange(prob.ny, device="cuda", dtype=torch.float32)
+    vel = torch.zeros(3, *prob.shape, device="cuda")
+    vel[0] = (0.5 * torch.tanh((y - prob.ny * 0.375) / 8.0))[None, :, None]
+    vel = vel.reshape(-1)
+    fld = torch.rand(3, n, generator=g, device="cuda")
+    outs = {k: torch.empty(m * n, device="cuda")
+            for k, m in (("E", 1), ("F", 3), ("P", 6), ("J", 1), ("H", 4), ("S", 4))}
+    stream = torch.cuda.current_stream()
+    call = lambda: L.lbrt_coupling(ctx, I, vel=vel, kappa_a=fld[0], kappa_s=fld[1], eta=fld[2],
+                                   stream=stream.cuda_stream, **outs)
+    call()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    for a, b in evs:
+        a.record(stream)
+        call()
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    bpc = prob.ndir * 4 + 24 + 19 * 4
+    ctx.close()
+    del I, outs, fld, vel
+    return {"workload": f"{prob.nx}^3 x {prob.ndir} FP32 state, sheared flow, all 19 outputs "
+                        "(FP64 sums)", "ms": round(ms, 4),
+            "bytes_per_cell_algorithmic": bpc,
+            "hbm_GBs_algorithmic": round(bpc * n / (ms * 1e-3) / 1e9, 1),
+            "frac_of_peak": round(bpc * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def time_batched(L, torch, ndomains=512, seed=4, sequential=True):
     """The batched opacity sweep: one lbrt_step_batched call against the same
     domains advanced one by one with lbrt_step (unless sequential=False).
@@ -421,8 +459,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=256, help="grid edge (default 256)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
-    ap.add_argument("--forms", default="bf16,fp16,collisions,batched,adjoint",
-                    help="extra forms to time (bf16, fp16, collisions, batched, adjoint)")
+    ap.add_argument("--forms", default="bf16,fp16,collisions,coupling,batched,adjoint",
+                    help="extra forms to time (bf16, fp16, collisions, coupling, batched, "
+                         "adjoint)")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batched form: skip the one-domain-at-a-time comparison")
     args = ap.parse_args()
@@ -476,6 +515,9 @@ def main():
         elif name == "collisions":
             log("timing the collision kinds")
             forms["collision_costs"] = time_collisions(L, torch, args.n, args.steps, args.warmup)
+        elif name == "coupling":
+            log("timing the coupling moments and sources")
+            forms["coupling"] = time_coupling(L, torch, prob)
         elif name == "batched":
             log("timing the batched sweep (512 domains)")
             try:

@@ -243,6 +243,46 @@ int lbrt_adjoint_step(lbrt_ctx *ctx, const void *I_n, const void *lam_next, void
  * stored state I; E, F as in lbrt_step (either may be NULL). */
 int lbrt_moments(lbrt_ctx *ctx, const void *I, void *E, void *F, void *stream);
 
+/*
+ * Outputs of lbrt_coupling, each a device array (NULL: not computed), in
+ * float64 for FP64 storage and float32 otherwise, component-major like F:
+ *   E  ncell      E = sum_i I_i                           (eq. moments_discrete)
+ *   F  3 x ncell  F^j = sum_i n_ij I_i
+ *   P  6 x ncell  P^xx, P^xy, P^xz, P^yy, P^yz, P^zz,
+ *                 P^jk = sum_i n_ij n_ik I_i              (eq. higher_moments)
+ *   J  ncell      fluid-frame energy density
+ *                 W^2 (E - 2 F.v + v.P.v)                 (eq. J)
+ *   H  4 x ncell  H_0, H_x, H_y, H_z: fluid-frame flux,
+ *                 H_j = W^3 (F.v - E) v_j + W h_ji (F^i - P^ik v_k),
+ *                 h_ij = W^2 v_i v_j + delta_ij            (eq. J);
+ *                 H_0 = v.H, the time component orthogonal to the fluid
+ *                 four-velocity (taken so that S_0 is the energy the
+ *                 collision takes from the radiation)
+ *   S  4 x ncell  S_0 = W (kappa_a J - eta) + k H_0,
+ *                 S_j = W (kappa_a J - eta) v_j + k H_j,
+ *                 k = kappa_a + kappa_s - kappa_1 / 3 with
+ *                 kappa_1 = lambda kappa_s / 3       (Sec. 5, coupling item 4)
+ */
+typedef struct {
+  void *E, *F, *P, *J, *H, *S;
+} lbrt_coupling_out;
+
+/* What the coupling loop of Sec. 5 (items 3 and 4) takes from a state I
+ * (storage type of the context) after a step: the lab-frame moments, the
+ * fluid-frame J and H, and the radiative sources, per cell, with every sum
+ * over directions in FP64.
+ *   vel      device, 3 x ncell float32 fluid velocity in units of c,
+ *            |v| < 1 (else the results are not finite); NULL: at rest;
+ *   kappa_a, kappa_s, eta  device, ncell float32 fluid-frame fields; needed
+ *            only for S (else LBRT_E_INVAL), may be NULL otherwise;
+ *   out      host struct of output pointers; outputs must not overlap I or
+ *            each other.
+ * The sources use lambda from the context.  One launch on `stream`; no
+ * allocation, so it may be captured in a graph. */
+int lbrt_coupling(lbrt_ctx *ctx, const void *I, const float *vel, const float *kappa_a,
+                  const float *kappa_s, const float *eta, const lbrt_coupling_out *out,
+                  void *stream);
+
 /* Convert a population array between storage types with the context's
  * per-direction scales (e.g. to encode an initial state for BF16/FP16
  * storage, or decode one for inspection).  src and dst must not overlap. */

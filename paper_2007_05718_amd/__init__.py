@@ -62,6 +62,10 @@ class lbrt_domain(ctypes.Structure):
                 ("E", ctypes.c_void_p), ("F", ctypes.c_void_p)]
 
 
+class lbrt_coupling_out(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("E", "F", "P", "J", "H", "S")]
+
+
 class LbrtError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"lbrt error {code}: {msg}")
@@ -90,6 +94,8 @@ def _load():
     lib.lbrt_step_noalloc.restype = ctypes.c_int
     lib.lbrt_moments.argtypes = [vp, vp, vp, vp, vp]
     lib.lbrt_moments.restype = ctypes.c_int
+    lib.lbrt_coupling.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(lbrt_coupling_out), vp]
+    lib.lbrt_coupling.restype = ctypes.c_int
     lib.lbrt_convert.argtypes = [vp, vp, i32, vp, i32, vp]
     lib.lbrt_convert.restype = ctypes.c_int
     lib.lbrt_adjoint_step.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp,
@@ -340,6 +346,25 @@ def lbrt_moments(ctx: Context, I, E=None, F=None, stream=None) -> None:
                              _ptr(F, "F", 3 * d.ncell, _moment_dtype(st)), _stream(stream)))
 
 
+def lbrt_coupling(ctx: Context, I, vel=None, kappa_a=None, kappa_s=None, eta=None,
+                  E=None, F=None, P=None, J=None, H=None, S=None, stream=None) -> None:
+    """Moments, fluid-frame J, H and the radiative sources of a state (the
+    C entry point of the same name); outputs not given are not computed."""
+    d = ctx.desc
+    st = d.c.storage
+    torch = _torch()
+    md = _moment_dtype(st)
+    n = d.ncell
+    out = lbrt_coupling_out(
+        _ptr(E, "E", n, md), _ptr(F, "F", 3 * n, md), _ptr(P, "P", 6 * n, md),
+        _ptr(J, "J", n, md), _ptr(H, "H", 4 * n, md), _ptr(S, "S", 4 * n, md))
+    _check(_lib.lbrt_coupling(
+        ctx.handle, _ptr(I, "I", d.ndir * n, _pop_dtype(st)),
+        _ptr(vel, "vel", 3 * n, torch.float32), _ptr(kappa_a, "kappa_a", n, torch.float32),
+        _ptr(kappa_s, "kappa_s", n, torch.float32), _ptr(eta, "eta", n, torch.float32),
+        ctypes.byref(out), _stream(stream)))
+
+
 def lbrt_convert(ctx: Context, src, src_storage: int, dst, dst_storage: int,
                  stream=None) -> None:
     d = ctx.desc
@@ -428,7 +453,7 @@ def lbrt_stream_copy(src, dst, stream=None) -> None:
 def exported_symbols() -> list:
     """Names of the C entry points the binding wraps."""
     return ["lbrt_validate", "lbrt_init", "lbrt_destroy", "lbrt_step", "lbrt_step_noalloc",
-            "lbrt_moments",
+            "lbrt_moments", "lbrt_coupling",
             "lbrt_convert", "lbrt_adjoint_step", "lbrt_set_tiling", "lbrt_get_tiling",
             "lbrt_batch_create", "lbrt_step_batched", "lbrt_batch_destroy", "lbrt_stream_copy",
             "lbrt_last_error"]

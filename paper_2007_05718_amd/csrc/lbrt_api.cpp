@@ -71,7 +71,7 @@ struct lbrt_ctx {
   std::vector<int> order;         // processing index -> storage plane
   void *tab_dev = nullptr;        // DirTab<float> or DirTab<double>, nb entries
   size_t tab_bytes = 0;
-  void *tab_moments_dev = nullptr;
+  CoupDir *coup_dev = nullptr;    // the coupling pass's direction table
   double *scales_dev = nullptr;   // per storage plane
   double *partials = nullptr;     // per-block sums of the step kernel
   int partials_cap = 0;
@@ -805,6 +805,18 @@ int lbrt_init(const lbrt_desc *d, lbrt_ctx **out) {
   if (e == hipSuccess)
     e = hipMemcpy(c->scales_dev, c->scales.data(), sizeof(double) * d->ndir,
                   hipMemcpyHostToDevice);
+  {
+    std::vector<CoupDir> cd(d->ndir);
+    for (int i = 0; i < d->ndir; ++i) {
+      const double *n = &c->dirs[3 * i];
+      cd[i] = CoupDir{{n[0], n[1], n[2]},
+                      {n[0] * n[0], n[0] * n[1], n[0] * n[2], n[1] * n[1], n[1] * n[2], n[2] * n[2]},
+                      c->scales[i]};
+    }
+    if (e == hipSuccess) e = hipMalloc(&c->coup_dev, sizeof(CoupDir) * d->ndir);
+    if (e == hipSuccess)
+      e = hipMemcpy(c->coup_dev, cd.data(), sizeof(CoupDir) * d->ndir, hipMemcpyHostToDevice);
+  }
   if (e != hipSuccess) {
     rc = fail(e == hipErrorOutOfMemory ? LBRT_E_NOMEM : LBRT_E_HIP, "lbrt_init: %s",
               hipGetErrorString(e));
@@ -857,6 +869,7 @@ void lbrt_destroy(lbrt_ctx *c) {
   if (c->pair_tab_dev) (void)hipFree(c->pair_tab_dev);
   if (c->pair_coll_dev) (void)hipFree(c->pair_coll_dev);
   if (c->scales_dev) (void)hipFree(c->scales_dev);
+  if (c->coup_dev) (void)hipFree(c->coup_dev);
   if (c->partials) (void)hipFree(c->partials);
   if (c->inflow_dev) (void)hipFree(c->inflow_dev);
   for (auto &m : c->plan)
@@ -957,6 +970,35 @@ int lbrt_moments(lbrt_ctx *c, const void *I, void *E, void *F, void *stream) {
   if (!c) return fail(LBRT_E_INVAL, "ctx is NULL");
   if (!I) return fail(LBRT_E_INVAL, "I is NULL");
   return moments_impl(c, I, E, F, static_cast<hipStream_t>(stream));
+}
+
+int lbrt_coupling(lbrt_ctx *c, const void *I, const float *vel, const float *kappa_a,
+                  const float *kappa_s, const float *eta, const lbrt_coupling_out *out,
+                  void *stream) {
+  if (!c) return fail(LBRT_E_INVAL, "ctx is NULL");
+  if (!I) return fail(LBRT_E_INVAL, "I is NULL");
+  if (!out) return fail(LBRT_E_INVAL, "out is NULL");
+  if (out->S && (!kappa_a || !kappa_s || !eta))
+    return fail(LBRT_E_INVAL, "the sources S need kappa_a, kappa_s and eta");
+  if (!out->E && !out->F && !out->P && !out->J && !out->H && !out->S) return LBRT_OK;
+  const lbrt_desc &d = c->desc;
+  CoupArgs a{};
+  a.E = out->E;
+  a.F = out->F;
+  a.P = out->P;
+  a.J = out->J;
+  a.H = out->H;
+  a.S = out->S;
+  a.vel = vel;
+  a.kappa_a = kappa_a;
+  a.kappa_s = kappa_s;
+  a.eta = eta;
+  a.ks_factor = 1.0 - d.lambda_aniso / 9.0;
+  a.ncell = (int64_t)d.nx * d.ny * d.nz;
+  a.ndir = d.ndir;
+  hipError_t e = launch_coupling(d.storage, I, c->coup_dev, a, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "lbrt_coupling");
+  return LBRT_OK;
 }
 
 int lbrt_convert(lbrt_ctx *c, const void *src, int32_t src_storage, void *dst,

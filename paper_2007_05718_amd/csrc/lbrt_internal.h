@@ -242,6 +242,26 @@ BatchLauncher batch_launcher(int storage, int bucket_index, bool moving);
 
 hipError_t launch_moments(int storage, const void *I, const void *tab, const KParams &p,
                           void *E, void *F, hipStream_t s);
+
+// One direction of the coupling pass: n, the six products n_a n_b (xx, xy,
+// xz, yy, yz, zz) and the storage scale, all FP64 (80 bytes).
+struct CoupDir {
+  double n[3];
+  double nn[6];
+  double s;
+};
+static_assert(sizeof(CoupDir) == 80, "CoupDir layout");
+
+// Outputs (any may be null), the fluid inputs and the sizes of a coupling pass.
+struct CoupArgs {
+  void *E, *F, *P, *J, *H, *S;
+  const float *vel, *kappa_a, *kappa_s, *eta;
+  double ks_factor;   // 1 - lambda / 9: k_s = k_0 - k_1 / 3 with k_1 = lambda k_0 / 3
+  int64_t ncell;
+  int ndir;
+};
+hipError_t launch_coupling(int storage, const void *I, const CoupDir *dir, const CoupArgs &a,
+                           hipStream_t s);
 hipError_t launch_convert(const void *src, int src_storage, void *dst, int dst_storage,
                           const double *scales_dev, int ndir, int64_t ncell, hipStream_t s);
 // Reduces the step kernel's per-block partials (nblocks rows of
