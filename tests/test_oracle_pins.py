@@ -23,6 +23,29 @@ def _problem(shape=(6, 7, 8), npoints=14, dt=0.5, bc=(wl.BC_OUTFLOW,) * 6, seed=
 # ---------------------------------------------------------------------------
 # Quadrature (Sec. 3.2.1: eqs. iso-tensors, isotropy-cond, sph-quad-cond)
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n_theta,n_phi", [(2, 4), (6, 8), (8, 14), (10, 20)])
+def test_gauss_legendre_product_exactness(n_theta, n_phi):
+    """The product rule (Sec. 3.2.1) integrates every monomial of degree up
+    to min(2 n_theta - 1, n_phi - 1) exactly (against the closed-form sphere
+    averages), fails some monomial one degree higher, has positive weights
+    summing to 1, and is centrally symmetric for even n_phi."""
+    dirs, w = wl.gauss_legendre_product(n_theta, n_phi)
+    p = wl.gauss_legendre_degree(n_theta, n_phi)
+    assert len(w) == n_theta * n_phi and np.all(w > 0) and abs(w.sum() - 1.0) < 1e-14
+    err = {}
+    for a in range(p + 2):
+        for b in range(p + 2 - a):
+            for c in range(p + 2 - a - b):
+                q = np.sum(w * dirs[:, 0] ** a * dirs[:, 1] ** b * dirs[:, 2] ** c)
+                err[(a, b, c)] = abs(q - analytic.monomial_average(a, b, c))
+    assert max(e for k, e in err.items() if sum(k) <= p) < 1e-14
+    assert max(e for k, e in err.items() if sum(k) == p + 1) > 1e-6
+    # central symmetry: -n_i is a node with the same weight
+    for i in range(len(w)):
+        j = int(np.argmin(np.linalg.norm(dirs + dirs[i], axis=1)))
+        assert np.linalg.norm(dirs[j] + dirs[i]) < 1e-14 and w[j] == w[i]
+
+
 @pytest.mark.parametrize("npoints", [6, 14, 26, 38, 50, 74, 86, 110, 146])
 def test_lebedev_monomial_exactness(npoints):
     dirs, w = wl.lebedev(npoints)
@@ -543,6 +566,28 @@ def test_sources_are_the_moving_collision_exchange(npoints):
 # ---------------------------------------------------------------------------
 # Whole steps
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("rule", [("lebedev", 26), ("gl", 4, 6)])
+def test_free_wave_moves_each_direction_at_unit_speed(rule):
+    """The spherical wave of Sec. 4.1.2 on a small box, before its front
+    reaches a face (its support, not only its front): the total energy is
+    conserved, and each direction's
+    distribution keeps its mass and moves its centroid by n_i dt per step
+    (the pull's weights sum to 1 and their first moment along each axis is
+    dt n^a: the interpolation is exact for linear fields)."""
+    # the pull widens the support by at most one cell per step and axis:
+    # radius + steps + 1 < 16 keeps it off the faces
+    p = wl.free_wave(n=32, rule=rule, radius=4.0, dt=0.2, steps=10)
+    I = orc.run(p)
+    z, y, x = np.meshgrid(*(np.arange(32.0),) * 3, indexing="ij")
+    pos = np.stack([x, y, z])
+    t = p.steps * p.dt
+    assert abs(orc.total_energy(I) / orc.total_energy(p.I0) - 1.0) < 1e-13
+    for i in range(p.ndir):
+        m0, m1 = p.I0[i].sum(), I[i].sum()
+        assert abs(m1 / m0 - 1.0) < 1e-13
+        c0 = (pos * p.I0[i]).reshape(3, -1).sum(axis=1) / m0
+        c1 = (pos * I[i]).reshape(3, -1).sum(axis=1) / m1
+        assert np.max(np.abs(c1 - c0 - t * p.dirs[i])) < 1e-12
 def test_diffusion_moments_follow_exact_recursion():
     """Pure isotropic scattering: the total energy and its x-moments after
     each step equal the exact per-direction moment recursion."""

@@ -12,7 +12,9 @@ Workload shapes follow the paper's tests (Sec. 4 and Sec. 5):
 * ``beams``      crossing beams plus an opaque obstacle (Sec. 4.1.1, 4.2.1),
 * ``batch``      many independent small domains of uneven size and opacity,
 * ``moving``     a relativistic shear flow with a log-normal absorption field
-                 (mixed-frame equation of App. B).
+                 (mixed-frame equation of App. B),
+* ``free_wave``  a spherical wave in vacuum (Sec. 4.1.2), on a Lebedev or a
+                 Gauss-Legendre product rule (Sec. 3.2.1).
 
 Conventions: dx = 1, cell centres at (i + 1/2), arrays are indexed
 ``[z, y, x]`` with x fastest, populations ``[dir, z, y, x]`` and are
@@ -55,6 +57,37 @@ def lebedev(npoints: int) -> Tuple[np.ndarray, np.ndarray]:
 
 def lebedev_degree(npoints: int) -> int:
     return LEBEDEV_ORDERS[npoints]
+
+
+def gauss_legendre_product(n_theta: int, n_phi: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Product rule on the sphere (Sec. 3.2.1, Gauss-Legendre quadrature):
+    ``n_theta`` Gauss-Legendre nodes in mu = cos(theta) (numpy's leggauss)
+    times ``n_phi`` equally spaced azimuths phi_j = 2 pi (j + 1/2) / n_phi
+    (the trapezoidal rule), weights a_k / (2 n_phi) so that they sum to 1.
+    Integrates the spherical harmonics of degree below
+    min(2 n_theta, n_phi) exactly; with n_phi even the node set is centrally
+    symmetric.  Returns unit directions ``(N, 3)`` and weights ``(N,)``."""
+    mu, a = np.polynomial.legendre.leggauss(n_theta)
+    phi = 2.0 * np.pi * (np.arange(n_phi) + 0.5) / n_phi
+    st = np.sqrt(1.0 - mu ** 2)
+    dirs = np.stack([np.outer(st, np.cos(phi)).ravel(), np.outer(st, np.sin(phi)).ravel(),
+                     np.repeat(mu, n_phi)], axis=1)
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    w = np.repeat(a / (2.0 * n_phi), n_phi)
+    return np.ascontiguousarray(dirs), w
+
+
+def gauss_legendre_degree(n_theta: int, n_phi: int) -> int:
+    return min(2 * n_theta - 1, n_phi - 1)
+
+
+def quadrature(rule) -> Tuple[np.ndarray, np.ndarray]:
+    """``("lebedev", npoints)`` or ``("gl", n_theta, n_phi)``."""
+    if rule[0] == "lebedev":
+        return lebedev(rule[1])
+    if rule[0] == "gl":
+        return gauss_legendre_product(rule[1], rule[2])
+    raise ValueError(f"unknown rule {rule!r}")
 
 
 def nearest_direction(dirs: np.ndarray, target: Sequence[float]) -> int:
@@ -140,6 +173,28 @@ def sphere(n: int = 32, npoints: int = 50, radius: float = 8.0,
         bc=(BC_OUTFLOW,) * 6, kappa_a=ka, kappa_s=np.zeros_like(ka), eta=ka.copy(),
         I0=_zero_state(len(w), n, n, n), steps=steps,
         meta={"radius": radius, "kappa": kappa, "centre": n / 2},
+    )
+
+
+# ---------------------------------------------------------------------------
+# Spherical wave in the free-streaming regime (Sec. 4.1.2).
+# ---------------------------------------------------------------------------
+def free_wave(n: int = 200, rule=("lebedev", 194), radius: float = 16.0, dt: float = 0.2,
+              steps: int = 200, alloc_state: bool = True) -> Problem:
+    """Vacuum (no absorption, emission or scattering), outflow faces, an
+    isotropic unit intensity inside a centred sphere of ``radius`` cells:
+    I_i = w_i (E = 1) where the cell centre is inside, 0 elsewhere."""
+    dirs, w = quadrature(rule)
+    c = _centres(n)
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    inside = ((x - n / 2) ** 2 + (y - n / 2) ** 2 + (z - n / 2) ** 2) < radius ** 2
+    I0 = (w[:, None, None, None] * inside[None]) if alloc_state else np.zeros((0,))
+    zeros = np.zeros((n, n, n), dtype=np.float32)
+    name = "wave%d_%s" % (n, "_".join(str(v) for v in rule))
+    return Problem(
+        name=name, nx=n, ny=n, nz=n, dt=dt, dirs=dirs, weights=w, bc=(BC_OUTFLOW,) * 6,
+        kappa_a=zeros, kappa_s=zeros.copy(), eta=zeros.copy(), I0=I0, steps=steps,
+        meta={"radius": radius, "centre": n / 2, "rule": tuple(rule)},
     )
 
 
