@@ -74,7 +74,7 @@ typedef enum {
   LBRT_COLL_LAMBDA = 2      /* Lambda iteration, lambda_iters cycles (Sec. 3.3)  */
 } lbrt_collision;
 
-enum { LBRT_MAX_DIRS = 152, LBRT_MAX_INFLOW = 32, LBRT_DIAG_LEN = 9 };
+enum { LBRT_MAX_DIRS = 200, LBRT_MAX_INFLOW = 32, LBRT_DIAG_LEN = 9 };
 
 /* Face order used by bc[], inflow planes and diagnostics. */
 enum { LBRT_FACE_MX = 0, LBRT_FACE_PX = 1, LBRT_FACE_MY = 2, LBRT_FACE_PY = 3,

@@ -26,7 +26,7 @@ LBRT_BC_OUTFLOW, LBRT_BC_PERIODIC, LBRT_BC_INFLOW = 0, 1, 2
 LBRT_FP32, LBRT_FP64, LBRT_BF16, LBRT_FP16 = 0, 1, 2, 3
 LBRT_COLL_IMPLICIT, LBRT_COLL_EXPLICIT, LBRT_COLL_LAMBDA = 0, 1, 2
 LBRT_ROUND_STOCHASTIC, LBRT_ROUND_NEAREST = 0, 1
-LBRT_MAX_DIRS, LBRT_MAX_INFLOW, LBRT_DIAG_LEN = 152, 32, 9
+LBRT_MAX_DIRS, LBRT_MAX_INFLOW, LBRT_DIAG_LEN = 200, 32, 9
 
 STORAGE_BYTES = {LBRT_FP32: 4, LBRT_FP64: 8, LBRT_BF16: 2, LBRT_FP16: 2}
 STORAGE_NAMES = {LBRT_FP32: "fp32", LBRT_FP64: "fp64", LBRT_BF16: "bf16", LBRT_FP16: "fp16"}

@@ -184,7 +184,7 @@ constexpr int kZfaceGroups = 8;
 // Direction-count buckets with a compiled kernel (multiples of 8: four waves
 // times pairs).  Rules whose size is not a bucket run in the next larger
 // bucket, padded with null directions.
-constexpr int kBuckets[] = {16, 32, 56, 112, 152};
+constexpr int kBuckets[] = {16, 32, 56, 112, 152, 200};
 constexpr int kNumBuckets = sizeof(kBuckets) / sizeof(kBuckets[0]);
 
 // Launchers, one per (storage, bucket), defined in lbrt_step_*.hip.

@@ -2,7 +2,7 @@
 //
 // A block owns an xy tile of 64 cells (tx x ty, x fastest, one cell per lane)
 // and marches it through a range of z-planes.  Its NW wave64s (8 for the
-// 112- and 152-slot buckets, 4 below) split the direction slots: wave q
+// 112-, 152- and 200-slot buckets, 4 below) split the direction slots: wave q
 // streams the q-th share of the slots for the tile's 64 cells and keeps the
 // streamed values in registers.
 //
@@ -271,8 +271,13 @@ __device__ inline void block_sums(const double (&v)[M], double *out) {
 // for 2: under the 128-VGPR cap the compiler packs two loaded 16-bit values
 // per VGPR, which waits for every prefetched load as soon as it is issued;
 // with the looser bound it still allocates under 128 VGPRs, unpacked.
+// FP64 (the checking form) with 112 slots or more also asks for 2: its
+// values take two VGPRs each and would spill under 128.
 template <typename S>
-constexpr int waves_per_simd(int nb) { return sizeof(S) == 2 ? (nb >= 112 ? 2 : 3) : (nb >= 112 ? 4 : 3); }
+constexpr int waves_per_simd(int nb) {
+  return (sizeof(S) == 2 || (sizeof(S) == 8 && nb >= 112)) ? (nb >= 112 ? 2 : 3)
+                                                             : (nb >= 112 ? 4 : 3);
+}
 // Main path: slots whose four taps are in flight ahead of the slot being
 // interpolated, for M slots per wave (memory-level parallelism per wave;
 // each costs 4 VGPRs: 4 ahead fit the 128-VGPR budget at M = 14, 3 at 19).
