@@ -149,6 +149,11 @@ int default_zlen(int nz, int64_t xy_tiles, int64_t target) {
 constexpr int kPairX0 = 2;
 constexpr int kPairTile = 128;
 int pair_ntx(int nx) { return (nx + kPairTile - 1) / kPairTile; }
+// With periodic x the two face columns at each end of a row are general
+// (checked) tiles; otherwise the pair kernel computes the whole row.
+bool pair_face_columns(const lbrt_desc &d) {
+  return d.bc[LBRT_FACE_MX] == LBRT_BC_PERIODIC;
+}
 
 // A fixed random 32-bit constant per storage plane (splitmix64 of its index):
 // one of the three parts of an element's stochastic rounding bits.
@@ -328,8 +333,8 @@ KParams make_params(const lbrt_ctx *c, int mode) {
   p.main_ty0 = 1;
   if (mode == 1) {
     p.pair = 1;
-    p.pair_x0 = kPairX0;
-    p.pair_xend = d.nx - kPairX0;
+    p.pair_x0 = pair_face_columns(d) ? kPairX0 : 0;
+    p.pair_xend = d.nx - p.pair_x0;
     p.pair_tab = c->pair_tab_dev;
     p.pair_coll = c->pair_coll_dev;
     p.ntx = pair_ntx(d.nx);
@@ -426,10 +431,11 @@ int plan_tiles(lbrt_ctx *c, int mode, int variant, bool zlo_inflow, bool zhi_inf
       }
     }
   } else {
-    const int xa = kPairX0, xb = d.nx - kPairX0;
-    // the face columns, every row
-    for (int x0 : {0, xb})
-      for (int y0 = 0; y0 < d.ny; y0 += 32) add(x0, y0, x0 + kPairX0, d.ny, 1, 0, d.nz);
+    const int xa = pair_face_columns(d) ? kPairX0 : 0, xb = d.nx - xa;
+    // the face columns of a periodic x axis, every row
+    if (xa > 0)
+      for (int x0 : {0, xb})
+        for (int y0 = 0; y0 < d.ny; y0 += 32) add(x0, y0, x0 + kPairX0, d.ny, 1, 0, d.nz);
     // rows 0 and ny - 1 between them, and the interior rows' z ranges that
     // the pair kernel does not march
     for (int y = 0; y < d.ny; ++y) {
@@ -519,7 +525,9 @@ int build_inflow(const lbrt_ctx *c, const lbrt_inflow *inflow, int32_t ninflow,
   return LBRT_OK;
 }
 
-int total_partials(const KParams &p) { return p.nblocks + p.ngeneral + zface_blocks(p); }
+int total_partials(const KParams &p) {
+  return p.nblocks + p.ngeneral + zface_blocks(p) + xface_blocks(p);
+}
 
 // What a step call needs after its arguments are checked: the kernel
 // parameters (tile plan for the call's ghost planes) and the compact ghost
@@ -598,6 +606,10 @@ int run_steps(lbrt_ctx *c, const StepCall &call, void *I_a, void *I_b, const flo
       e = launch_zface(d.storage, src, c->tab_dev, p, table,
                        partials + (size_t)(p.nblocks + p.ngeneral) * kStepPartials, s);
       if (e != hipSuccess) return hip_fail(e, "lbrt_step: launching the z-face flux kernel");
+      e = launch_xface(d.storage, src, c->tab_dev, p,
+                       partials + (size_t)(p.nblocks + p.ngeneral + zface_blocks(p)) *
+                                      kStepPartials, s);
+      if (e != hipSuccess) return hip_fail(e, "lbrt_step: launching the x-face flux kernel");
     }
     if (last && (E || F)) pk.flags |= KF_WRITE_EF;
     e = call.launch(src, dst, kappa_a, kappa_s, eta, vel, c->tab_dev, pk, table,

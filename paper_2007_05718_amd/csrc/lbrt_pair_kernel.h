@@ -20,13 +20,21 @@
 // read with one wide scalar load per plane.
 //
 // The tiles start at x = 128 k, so a wave's row loads and stores are whole
-// cache lines; they compute the cells x in [2, nx - 2) of rows [1, ny - 1),
-// where every tap of a row is inside the box and no cell is on an x or y
-// face.  The columns x < 2, x >= nx - 2 (whose pairs these tiles load but do
-// not store) and the face rows are tiles of the general (checked) path.  A
-// face pair's neighbouring pair lies in the row before or after, which
-// exists for interior rows.  nx is even, so every pair starts at an even
-// cell index and its loads and stores are aligned.
+// cache lines; they compute rows [1, ny - 1), whose y halo is inside the box.
+// With non-periodic x faces they compute every cell of the row: the first
+// and last pair are face pairs, whose neighbouring pair for sx > 0 (first)
+// or sx < 0 (last) is a ghost: the lane loads its own pair in its place and
+// zeroes it; an inflow ghost plane on the face is added afterwards
+// (x_ghost_correction, as on the other paths).  The zeroing is two selects
+// per slot on every tile (a second copy of the slot loop for the face tiles
+// only would run the kernel out of scalar registers).  The x-face outflux of
+// the face cells is booked by xface_kernel.  With periodic x the tiles compute
+// x in [2, nx - 2) and the columns x < 2, x >= nx - 2 are tiles of the
+// general (checked) path, like the face rows.  nx is even, so every pair
+// starts at an even cell index and its loads and stores are aligned.
+// (Reading the face columns on the general path instead would fetch a whole
+// cache line of a row for each pair: for 16-bit storage that path took a
+// third of the step's time at 256^3.)
 //
 // Per plane:
 //   stream   the wave's slots for both cells (P from 4 row loads, issued a few
@@ -144,9 +152,10 @@ template <typename S, int NB, int NW = waves_for(NB)>
 __device__ __forceinline__ void
 march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__ ka,
            const float *__restrict__ ks, const float *__restrict__ eta,
-           const PairTab *__restrict__ tab, const PairColl *__restrict__ ctab, const KParams &p,
-           float *__restrict__ Eout, float *__restrict__ Fout, double *__restrict__ partials,
-           int x0, int y, int zb, int ze) {
+           const PairTab *__restrict__ tab, const PairColl *__restrict__ ctab,
+           const DirTab<float> *__restrict__ dtab, const InflowArgs *__restrict__ inflow,
+           const KParams &p, float *__restrict__ Eout, float *__restrict__ Fout,
+           double *__restrict__ partials, int x0, int y, int zb, int ze) {
   using IO = PairIO<S>;
   using R = typename IO::R;
   using T = float;
@@ -173,6 +182,11 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
   const bool valid = x >= p.pair_x0 && x < xend;
   if (x >= xend) x = xend - 2;
   const uint32_t o0 = (uint32_t)(x + nx * y) * (uint32_t)SZ;
+  // face pairs of a non-periodic x axis (pair_x0 = 0, pair_xend = nx then)
+  const int perx = p.periodic[0];
+  const bool lox = valid && !perx && x == 0;
+  const bool hix = valid && !perx && x + 2 == nx;
+  const bool xface_tile = !perx && (x0 == 0 || x0 + NC >= nx);
   // combine lanes: cell cc of the tile
   const int cc = (q & 1) * 64 + lane;
   int xc = x0 + cc;
@@ -186,16 +200,26 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
   // the four row loads of slot d from the z-plane starting at byte `plane`
   // (rows y and y - sy; own and neighbouring pair)
   // The neighbouring pair's shift goes into the wave-uniform base, so the
-  // four loads share the lane's offset o0 (scalar base + 32-bit lane offset).
+  // loads take a scalar base plus a 32-bit lane offset: o0 for the own pair;
+  // for the neighbouring pair o0 too, except on a lane whose pair is the
+  // first (sx > 0) or the last (sx < 0) of its row, whose neighbouring pair
+  // is outside the row: that lane reads its own pair again (its values are
+  // then zeroed, or unused), so that no load leaves the row, and no load
+  // leaves the state's buffer (the row before the first or after the last
+  // of a plane can be outside it).
+  const uint32_t onp = x == 0 ? o0 + IO::kShift : o0;
+  const uint32_t onm = x + 2 == nx ? o0 - IO::kShift : o0;
   auto load4 = [&](const PairTab &d, const char *plane, R (&v)[4]) {
     const char *r0 = plane + d.plane_off;
     const char *r1 = r0 + d.row_off;
-    const int sh = (d.flags & kPairSxPos) ? -(int)IO::kShift : (int)IO::kShift;
+    const bool pos = (d.flags & kPairSxPos) != 0;
+    const int sh = pos ? -(int)IO::kShift : (int)IO::kShift;
     const uint32_t oo = opaque_lane(o0);
+    const uint32_t on = opaque_lane(pos ? onp : onm);
     v[0] = IO::ld(r0, oo);
-    v[1] = IO::ld(r0 + sh, oo);
+    v[1] = IO::ld(r0 + sh, on);
     v[2] = IO::ld(r1, oo);
-    v[3] = IO::ld(r1 + sh, oo);
+    v[3] = IO::ld(r1 + sh, on);
   };
   // plane values of both cells from a slot's four loads
   auto interp2 = [&](const PairTab &d, const R (&v)[4], T &Plo, T &Phi) {
@@ -208,6 +232,18 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
   auto plane_above = [&](int z) {
     const int za = z + 1 < nz ? z + 1 : (perz ? 0 : nz - 1);
     return (int64_t)za * pc;
+  };
+
+  // Face lanes: the neighbouring pair of a slot whose x-shifted taps lie
+  // outside the box is a vacuum ghost (zeroed: its in-box load is
+  // discarded).  The x-face outflux of these cells is booked by
+  // xface_kernel (booking it here would keep more of each slot's record in
+  // scalar registers than the loop has).
+  double fin = 0.0;
+  auto zap = [&](const PairTab &d, R (&v)[4]) {
+    const bool z0 = (d.flags & kPairSxPos) ? lox : hix;
+    v[1] = z0 ? R(0) : v[1];
+    v[3] = z0 ? R(0) : v[3];
   };
 
   // prologue: the carried plane value of every slot and both cells
@@ -223,6 +259,7 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
         R v[4];
         const bool in = (unsigned)zl < (unsigned)nz;
         load4(d, in_bytes + (int64_t)min(max(zl, 0), nz - 1) * pc * SZ, v);
+        zap(d, v);
         T a, b;
         interp2(d, v, a, b);
         carry[J][0] = (in ? T(1) : T(0)) * a;
@@ -230,6 +267,19 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
       }
     };
     unroll<0, M>(pro);
+  }
+
+  // the slots of this wave with an inflow ghost plane on an x face that this
+  // tile touches (bit J for slot J)
+  uint32_t xgmask = 0u;
+  if ((p.flags & KF_XGHOSTS) && xface_tile) {
+    const bool tlo = x0 == 0, thi = x0 + NC >= nx;
+    auto scan = [&]<int J>() {
+      const DirTab<T> &d = dtab[q * M + J];
+      if (inflow->ghost[q * M + J][0] != nullptr && ((d.s[0] > 0 && tlo) || (d.s[0] < 0 && thi)))
+        xgmask |= 1u << J;
+    };
+    unroll<0, M>(scan);
   }
 
   __shared__ T red[NW][4][NC];
@@ -276,6 +326,7 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
         const PairTab &d = tb[J];
         if constexpr (J + D < M)
           load4(tb[J + D], (tb[J + D].flags & kPairDzn) ? p1 : p0, pf[J + D]);
+        zap(d, pf[J]);
         T Pn[2];
         interp2(d, pf[J], Pn[0], Pn[1]);
         const T wn = zero_if(d.wz_new, (int)((d.flags >> 1) & 1u) & gh);
@@ -295,6 +346,34 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
         }
       };
       unroll<0, M>(slot);
+    }
+    if (xgmask != 0u) {
+      // Inflow ghosts on the x faces enter after the vacuum sums, slot by
+      // slot, for the face cells of the directions with a ghost plane there
+      // (as on the other paths, so that all give the same bits).
+      auto body = [&]<int J>() {
+        if ((xgmask >> J) & 1u) {
+          const DirTab<T> &d = dtab[q * M + J];
+          const bool pos = d.s[0] > 0;
+          if (pos ? lox : hix) {
+            const T dI = x_ghost_correction<T>(d, inflow->ghost[q * M + J][0], y, z, p.ny, nz,
+                                               p.periodic[1], perz);
+            fin += (double)dI;
+            auto add = [&](int h) {
+              Is[J][h] += dI;
+              Es[h] += dI;
+              F0[h] = fma(d.n[0], dI, F0[h]);
+              F1[h] = fma(d.n[1], dI, F1[h]);
+              F2[h] = fma(d.n[2], dI, F2[h]);
+            };
+            if (pos)
+              add(0);
+            else
+              add(1);
+          }
+        }
+      };
+      unroll<0, M>(body);
     }
 
     // ---- the waves' partial sums of the 128 cells
@@ -376,6 +455,7 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
     for (int k = 0; k < kStepPartials; ++k) v[k] = 0.0;
     v[0] = sE;
     v[1] = sEs;
+    v[8] = fin;
     block_sums<kStepPartials, NW>(v, partials + (int64_t)blockIdx.x * kStepPartials);
   }
 }
@@ -386,6 +466,7 @@ __global__ void __launch_bounds__(64 * waves_for(NB), waves_per_simd<S>(NB))
 step_kernel_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__ ka,
                  const float *__restrict__ ks, const float *__restrict__ eta,
                  const PairTab *__restrict__ tab, const PairColl *__restrict__ ctab,
+                 const DirTab<float> *__restrict__ dtab, const InflowArgs *__restrict__ inflow,
                  const KParams p, float *__restrict__ Eout, float *__restrict__ Fout,
                  double *__restrict__ partials) {
   const int t = xcd_tile(blockIdx.x, p.nblocks);
@@ -394,8 +475,8 @@ step_kernel_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *_
   const int y = p.main_ty0 + r % p.main_nty;
   const int tzr = p.main_zr0 + r / p.main_nty;
   const int zb = tzr * p.zlen;
-  march_pair<S, NB>(Iin, Iout, ka, ks, eta, tab, ctab, p, Eout, Fout, partials, 128 * tix, y,
-                    zb, min(p.nz, zb + p.zlen));
+  march_pair<S, NB>(Iin, Iout, ka, ks, eta, tab, ctab, dtab, inflow, p, Eout, Fout, partials,
+                    128 * tix, y, zb, min(p.nz, zb + p.zlen));
 }
 
 }  // namespace lbrt

@@ -85,6 +85,6 @@ def test_validate_rejects_bad_descriptions():
     r /= np.linalg.norm(r, axis=1, keepdims=True)
     assert L.lbrt_validate(_desc(dirs=r, weights=np.full(40, 1 / 40))) == L.LBRT_E_QUAD
     # too many directions
-    assert L.lbrt_validate(_desc(dirs=np.tile(dirs, (4, 1)), weights=np.tile(w, 4) / 4)) \
+    assert L.lbrt_validate(_desc(dirs=np.tile(dirs, (5, 1)), weights=np.tile(w, 5) / 5)) \
         == L.LBRT_E_INVAL
     assert "ndir" in L.lbrt_last_error()
