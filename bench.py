@@ -76,11 +76,8 @@ def time_form(L, torch, prob, storage, steps, warmup, with_outputs=True):
     """Returns (mean ms per step over the timed region, mean kernel ms)."""
     desc = L.Desc.from_problem(prob, storage=storage)
     ctx = L.lbrt_init(desc)
-    n = prob.ndir * prob.ncell
-    dt = {L.LBRT_FP32: torch.float32, L.LBRT_BF16: torch.bfloat16,
-          L.LBRT_FP16: torch.float16, L.LBRT_FP64: torch.float64}[storage]
-    Ia = torch.zeros(n, dtype=dt, device="cuda")
-    Ib = torch.zeros(n, dtype=dt, device="cuda")
+    Ia = L.alloc_state(ctx).zero_()
+    Ib = L.alloc_state(ctx).zero_()
     f = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).reshape(-1).cuda()
     ka, ks, eta = f(prob.kappa_a), f(prob.kappa_s), f(prob.eta)
     inflow = [(p.face, p.direction, f(p.values)) for p in prob.inflow]
@@ -123,11 +120,8 @@ def kernel_only_ms(L, torch, prob, storage, steps):
     """Mean duration of the step kernel alone (E, F written, no diagnostics)."""
     desc = L.Desc.from_problem(prob, storage=storage)
     ctx = L.lbrt_init(desc)
-    n = prob.ndir * prob.ncell
-    dt = {L.LBRT_FP32: torch.float32, L.LBRT_BF16: torch.bfloat16,
-          L.LBRT_FP16: torch.float16}[storage]
-    Ia = torch.zeros(n, dtype=dt, device="cuda")
-    Ib = torch.zeros(n, dtype=dt, device="cuda")
+    Ia = L.alloc_state(ctx).zero_()
+    Ib = L.alloc_state(ctx).zero_()
     f = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).reshape(-1).cuda()
     ka, ks, eta = f(prob.kappa_a), f(prob.kappa_s), f(prob.eta)
     inflow = [(p.face, p.direction, f(p.values)) for p in prob.inflow]
@@ -185,11 +179,8 @@ def form_error(L, torch, storage) -> dict:
     ref = np.load(path)
     prob = wl.beams(n=int(ref["n"]), steps=int(ref["steps"]), alloc_state=False)
     ctx = L.lbrt_init(L.Desc.from_problem(prob, storage=storage))
-    dt = {L.LBRT_FP32: torch.float32, L.LBRT_BF16: torch.bfloat16,
-          L.LBRT_FP16: torch.float16}[storage]
-    n = prob.ndir * prob.ncell
-    Ia = torch.zeros(n, dtype=dt, device="cuda")
-    Ib = torch.zeros(n, dtype=dt, device="cuda")
+    Ia = L.alloc_state(ctx).zero_()
+    Ib = L.alloc_state(ctx).zero_()
     f = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).reshape(-1).cuda()
     inflow = [(p.face, p.direction, f(p.values)) for p in prob.inflow]
     E = torch.empty(prob.ncell, device="cuda")
@@ -459,9 +450,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=256, help="grid edge (default 256)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
-    ap.add_argument("--forms", default="bf16,fp16,collisions,coupling,batched,adjoint",
-                    help="extra forms to time (bf16, fp16, collisions, coupling, batched, "
-                         "adjoint)")
+    ap.add_argument("--forms",
+                    default="bf16,fp16,bf16_shifted,fp16_shifted,collisions,coupling,batched,"
+                            "adjoint",
+                    help="extra forms to time (bf16, fp16, bf16_shifted, fp16_shifted, "
+                         "collisions, coupling, batched, adjoint)")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batched form: skip the one-domain-at-a-time comparison")
     args = ap.parse_args()
@@ -494,16 +487,18 @@ def main():
     achieved = bytes_launch / (kms * 1e-3) / 1e9
     forms = {}
     names = [s for s in args.forms.split(",") if s]
-    if any(n in ("bf16", "fp16") for n in names):
+    if any(n.startswith(("bf16", "fp16")) for n in names):
         log("fp32 error against the oracle (64^3, 500 steps)")
         forms["fp32_error_vs_oracle"] = form_error(L, torch, L.LBRT_FP32)
     for name in names:
-        if name in ("bf16", "fp16"):
-            st = {"bf16": L.LBRT_BF16, "fp16": L.LBRT_FP16}[name]
+        if name in ("bf16", "fp16", "bf16_shifted", "fp16_shifted"):
+            st = {"bf16": L.LBRT_BF16, "fp16": L.LBRT_FP16, "bf16_shifted": L.LBRT_BF16_SHIFTED,
+                  "fp16_shifted": L.LBRT_FP16_SHIFTED}[name]
             log(f"timing {name}")
             w2, c2, _ = time_form(L, torch, prob, st, args.steps, args.warmup)
             k2 = kernel_only_ms(L, torch, prob, st, args.steps)
-            b2 = algorithmic_bytes_per_cell(ndir, 2) * ncell
+            # (the shifted forms also read and write the cell's FP32 E: 8 B)
+            b2 = (algorithmic_bytes_per_cell(ndir, 2) + (8 if "shifted" in name else 0)) * ncell
             forms[name] = {
                 "GDUPS": round(updates / (w2 * 1e-3) / 1e9, 2),
                 "ms_per_step": round(w2, 4),

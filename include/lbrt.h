@@ -61,7 +61,23 @@ typedef enum {
 } lbrt_status;
 
 typedef enum { LBRT_BC_OUTFLOW = 0, LBRT_BC_PERIODIC = 1, LBRT_BC_INFLOW = 2 } lbrt_bc;
-typedef enum { LBRT_FP32 = 0, LBRT_FP64 = 1, LBRT_BF16 = 2, LBRT_FP16 = 3 } lbrt_storage;
+/* Population storage.  The equilibrium-shifted forms store the deviation
+ * d_i = (I_i - w_i E) / s_i of each population from the cell's isotropic
+ * equilibrium in BF16 or FP16, and the cell's E in FP32 after them: a state
+ * is ndir * ncell 16-bit values, then (at byte lbrt_state_e_offset, the
+ * first multiple of 256 at or after 2 ndir ncell) ncell float32 values; its
+ * size is lbrt_state_bytes.  In optically thick cells I_i is close to
+ * w_i E, and the deviation keeps F (a small difference of populations of
+ * size w_i E) to the 16-bit format's relative precision.  Static fluid only;
+ * the interior runs on the one-cell-per-lane kernel. */
+typedef enum {
+  LBRT_FP32 = 0,
+  LBRT_FP64 = 1,
+  LBRT_BF16 = 2,
+  LBRT_FP16 = 3,
+  LBRT_BF16_SHIFTED = 4,
+  LBRT_FP16_SHIFTED = 5
+} lbrt_storage;
 /* Rounding of populations stored as BF16/FP16 (ignored for FP32/FP64). */
 typedef enum {
   LBRT_ROUND_STOCHASTIC = 0, /* round up with the probability of the dropped
@@ -134,6 +150,13 @@ typedef struct {
   int32_t dir;
   const float *values;
 } lbrt_inflow;
+
+/* Bytes of one state buffer of a problem: ndir * ncell elements of the
+ * storage type, plus the E array for the equilibrium-shifted forms; and the
+ * byte offset of that E array (0 for the other forms).  Host only; -1 for a
+ * storage value that is not a storage type. */
+int64_t lbrt_state_bytes(int32_t storage, int32_t ndir, int64_t ncell);
+int64_t lbrt_state_e_offset(int32_t storage, int32_t ndir, int64_t ncell);
 
 /* Host-only check of a problem statement; needs no GPU.  Rejects
  * dt <= 0 or dt > dx (LBRT_E_CFL), dims < 2, ndir outside [2, LBRT_MAX_DIRS],

@@ -24,6 +24,7 @@ LBRT_OK, LBRT_E_INVAL, LBRT_E_CFL, LBRT_E_QUAD = 0, -1, -2, -3
 LBRT_E_NOMEM, LBRT_E_HIP, LBRT_E_UNSUPPORTED = -4, -5, -6
 LBRT_BC_OUTFLOW, LBRT_BC_PERIODIC, LBRT_BC_INFLOW = 0, 1, 2
 LBRT_FP32, LBRT_FP64, LBRT_BF16, LBRT_FP16 = 0, 1, 2, 3
+LBRT_BF16_SHIFTED, LBRT_FP16_SHIFTED = 4, 5
 LBRT_COLL_IMPLICIT, LBRT_COLL_EXPLICIT, LBRT_COLL_LAMBDA = 0, 1, 2
 LBRT_ROUND_STOCHASTIC, LBRT_ROUND_NEAREST = 0, 1
 LBRT_MAX_DIRS, LBRT_MAX_INFLOW, LBRT_DIAG_LEN = 200, 32, 9
@@ -96,6 +97,10 @@ def _load():
     lib.lbrt_moments.restype = ctypes.c_int
     lib.lbrt_coupling.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(lbrt_coupling_out), vp]
     lib.lbrt_coupling.restype = ctypes.c_int
+    lib.lbrt_state_bytes.argtypes = [i32, i32, ctypes.c_int64]
+    lib.lbrt_state_bytes.restype = ctypes.c_int64
+    lib.lbrt_state_e_offset.argtypes = [i32, i32, ctypes.c_int64]
+    lib.lbrt_state_e_offset.restype = ctypes.c_int64
     lib.lbrt_convert.argtypes = [vp, vp, i32, vp, i32, vp]
     lib.lbrt_convert.restype = ctypes.c_int
     lib.lbrt_adjoint_step.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp,
@@ -251,6 +256,47 @@ def _pop_dtype(storage: int):
             LBRT_FP16: (torch.float16, torch.int16, torch.uint16)}[storage]
 
 
+def _is_shifted(storage: int) -> bool:
+    return storage in (LBRT_BF16_SHIFTED, LBRT_FP16_SHIFTED)
+
+
+def state_bytes(storage: int, ndir: int, ncell: int) -> int:
+    """Bytes of one state buffer (lbrt_state_bytes)."""
+    v = _lib.lbrt_state_bytes(int(storage), int(ndir), int(ncell))
+    if v < 0:
+        raise ValueError(f"storage {storage} is not a storage type")
+    return int(v)
+
+
+def state_e_offset(storage: int, ndir: int, ncell: int) -> int:
+    """Byte offset of the E array of an equilibrium-shifted state (else 0)."""
+    return int(_lib.lbrt_state_e_offset(int(storage), int(ndir), int(ncell)))
+
+
+def alloc_state(ctx: "Context", storage: Optional[int] = None):
+    """An uninitialised state buffer on the GPU for the context's problem (a
+    uint8 tensor of lbrt_state_bytes for the equilibrium-shifted forms, else
+    a tensor of the storage type)."""
+    torch = _torch()
+    d = ctx.desc
+    st = d.c.storage if storage is None else storage
+    if _is_shifted(st):
+        return torch.empty(state_bytes(st, d.ndir, d.ncell), dtype=torch.uint8, device="cuda")
+    dt = {LBRT_FP32: torch.float32, LBRT_FP64: torch.float64, LBRT_BF16: torch.bfloat16,
+          LBRT_FP16: torch.float16}[st]
+    return torch.empty(d.ndir * d.ncell, dtype=dt, device="cuda")
+
+
+def _state(t, what: str, desc: "Desc", storage: Optional[int] = None):
+    """Pointer of a state buffer, checked against the problem's size: a
+    tensor of the storage type with ndir * ncell elements, or for the
+    equilibrium-shifted forms a uint8 tensor of lbrt_state_bytes."""
+    st = desc.c.storage if storage is None else storage
+    if _is_shifted(st):
+        return _ptr(t, what, state_bytes(st, desc.ndir, desc.ncell), _torch().uint8)
+    return _ptr(t, what, desc.ndir * desc.ncell, _pop_dtype(st))
+
+
 def _moment_dtype(storage: int):
     torch = _torch()
     return torch.float64 if storage == LBRT_FP64 else torch.float32
@@ -288,8 +334,8 @@ def lbrt_step(ctx: Context, I_a, I_b, kappa_a, kappa_s, eta, vel=None, inflow=No
     planes, nin = _inflow_planes(d, inflow)
     f32 = _torch().float32
     rc = _lib.lbrt_step(
-        ctx.handle, _ptr(I_a, "I_a", n * nc, _pop_dtype(st)),
-        _ptr(I_b, "I_b", n * nc, _pop_dtype(st)),
+        ctx.handle, _state(I_a, "I_a", d),
+        _state(I_b, "I_b", d),
         _ptr(kappa_a, "kappa_a", nc, f32), _ptr(kappa_s, "kappa_s", nc, f32),
         _ptr(eta, "eta", nc, f32), _ptr(vel, "vel", 3 * nc, f32), planes, nin, int(nsteps),
         _ptr(E, "E", nc, _moment_dtype(st)), _ptr(F, "F", 3 * nc, _moment_dtype(st)),
@@ -307,8 +353,8 @@ def lbrt_step_noalloc(ctx: Context, I_a, I_b, kappa_a, kappa_s, eta, vel=None, i
     planes, nin = _inflow_planes(d, inflow)
     f32 = _torch().float32
     rc = _lib.lbrt_step_noalloc(
-        ctx.handle, _ptr(I_a, "I_a", n * nc, _pop_dtype(st)),
-        _ptr(I_b, "I_b", n * nc, _pop_dtype(st)),
+        ctx.handle, _state(I_a, "I_a", d),
+        _state(I_b, "I_b", d),
         _ptr(kappa_a, "kappa_a", nc, f32), _ptr(kappa_s, "kappa_s", nc, f32),
         _ptr(eta, "eta", nc, f32), _ptr(vel, "vel", 3 * nc, f32), planes, nin, int(nsteps),
         _ptr(E, "E", nc, _moment_dtype(st)), _ptr(F, "F", 3 * nc, _moment_dtype(st)),
@@ -328,9 +374,9 @@ def lbrt_adjoint_step(ctx: Context, I_n, lam_next, lam_out, detector_face: int, 
     f32 = _torch().float32
     gdt = _moment_dtype(st)
     _check(_lib.lbrt_adjoint_step(
-        ctx.handle, _ptr(I_n, "I_n", n * nc, _pop_dtype(st)),
-        _ptr(lam_next, "lam_next", n * nc, _pop_dtype(st)),
-        _ptr(lam_out, "lam_out", n * nc, _pop_dtype(st)), int(detector_face),
+        ctx.handle, _state(I_n, "I_n", d),
+        _state(lam_next, "lam_next", d),
+        _state(lam_out, "lam_out", d), int(detector_face),
         _ptr(g_kappa_a, "g_kappa_a", nc, gdt), _ptr(g_kappa_s, "g_kappa_s", nc, gdt),
         _ptr(g_eta, "g_eta", nc, gdt),
         _ptr(kappa_a, "kappa_a", nc, f32), _ptr(kappa_s, "kappa_s", nc, f32),
@@ -341,7 +387,7 @@ def lbrt_adjoint_step(ctx: Context, I_n, lam_next, lam_out, detector_face: int, 
 def lbrt_moments(ctx: Context, I, E=None, F=None, stream=None) -> None:
     d = ctx.desc
     st = d.c.storage
-    _check(_lib.lbrt_moments(ctx.handle, _ptr(I, "I", d.ndir * d.ncell, _pop_dtype(st)),
+    _check(_lib.lbrt_moments(ctx.handle, _state(I, "I", d),
                              _ptr(E, "E", d.ncell, _moment_dtype(st)),
                              _ptr(F, "F", 3 * d.ncell, _moment_dtype(st)), _stream(stream)))
 
@@ -359,7 +405,7 @@ def lbrt_coupling(ctx: Context, I, vel=None, kappa_a=None, kappa_s=None, eta=Non
         _ptr(E, "E", n, md), _ptr(F, "F", 3 * n, md), _ptr(P, "P", 6 * n, md),
         _ptr(J, "J", n, md), _ptr(H, "H", 4 * n, md), _ptr(S, "S", 4 * n, md))
     _check(_lib.lbrt_coupling(
-        ctx.handle, _ptr(I, "I", d.ndir * n, _pop_dtype(st)),
+        ctx.handle, _state(I, "I", d),
         _ptr(vel, "vel", 3 * n, torch.float32), _ptr(kappa_a, "kappa_a", n, torch.float32),
         _ptr(kappa_s, "kappa_s", n, torch.float32), _ptr(eta, "eta", n, torch.float32),
         ctypes.byref(out), _stream(stream)))
@@ -368,9 +414,8 @@ def lbrt_coupling(ctx: Context, I, vel=None, kappa_a=None, kappa_s=None, eta=Non
 def lbrt_convert(ctx: Context, src, src_storage: int, dst, dst_storage: int,
                  stream=None) -> None:
     d = ctx.desc
-    n = d.ndir * d.ncell
-    _check(_lib.lbrt_convert(ctx.handle, _ptr(src, "src", n, _pop_dtype(src_storage)),
-                             int(src_storage), _ptr(dst, "dst", n, _pop_dtype(dst_storage)),
+    _check(_lib.lbrt_convert(ctx.handle, _state(src, "src", d, src_storage),
+                             int(src_storage), _state(dst, "dst", d, dst_storage),
                              int(dst_storage), _stream(stream)))
 
 
@@ -415,8 +460,8 @@ def lbrt_batch_create(domains) -> Batch:
         d = ctx.desc
         n, nc, st = d.ndir, d.ncell, d.c.storage
         arr[k].ctx = ctx.handle.value
-        arr[k].I_a = _ptr(dm["I_a"], f"domains[{k}].I_a", n * nc, _pop_dtype(st)).value
-        arr[k].I_b = _ptr(dm["I_b"], f"domains[{k}].I_b", n * nc, _pop_dtype(st)).value
+        arr[k].I_a = _state(dm["I_a"], f"domains[{k}].I_a", d).value
+        arr[k].I_b = _state(dm["I_b"], f"domains[{k}].I_b", d).value
         arr[k].kappa_a = _ptr(dm["kappa_a"], "kappa_a", nc, f32).value
         arr[k].kappa_s = _ptr(dm["kappa_s"], "kappa_s", nc, f32).value
         arr[k].eta = _ptr(dm["eta"], "eta", nc, f32).value
@@ -453,7 +498,7 @@ def lbrt_stream_copy(src, dst, stream=None) -> None:
 def exported_symbols() -> list:
     """Names of the C entry points the binding wraps."""
     return ["lbrt_validate", "lbrt_init", "lbrt_destroy", "lbrt_step", "lbrt_step_noalloc",
-            "lbrt_moments", "lbrt_coupling",
+            "lbrt_moments", "lbrt_coupling", "lbrt_state_bytes", "lbrt_state_e_offset",
             "lbrt_convert", "lbrt_adjoint_step", "lbrt_set_tiling", "lbrt_get_tiling",
             "lbrt_batch_create", "lbrt_step_batched", "lbrt_batch_destroy", "lbrt_stream_copy",
             "lbrt_last_error"]

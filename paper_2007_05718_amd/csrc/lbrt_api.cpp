@@ -42,6 +42,22 @@ size_t storage_bytes(int s) {
   }
 }
 
+bool is_shifted(int s) { return s == LBRT_BF16_SHIFTED || s == LBRT_FP16_SHIFTED; }
+bool is_reduced(int s) {
+  return s == LBRT_BF16 || s == LBRT_FP16 || is_shifted(s);
+}
+
+// Byte offset of the E array in an equilibrium-shifted state (0 otherwise)
+// and the bytes of one state buffer.
+int64_t e_offset(int s, int ndir, int64_t ncell) {
+  if (!is_shifted(s)) return 0;
+  return (2 * (int64_t)ndir * ncell + 255) / 256 * 256;
+}
+int64_t state_bytes(int s, int ndir, int64_t ncell) {
+  if (is_shifted(s)) return e_offset(s, ndir, ncell) + 4 * ncell;
+  return (int64_t)storage_bytes(s) * ndir * ncell;
+}
+
 struct TileShape { int tx, ty; };
 
 // Device memory of lbrt_step_noalloc, for callers that cannot allocate: the
@@ -73,6 +89,7 @@ struct lbrt_ctx {
   size_t tab_bytes = 0;
   CoupDir *coup_dev = nullptr;    // the coupling pass's direction table
   double *scales_dev = nullptr;   // per storage plane
+  double *weights_dev = nullptr;  // per storage plane (shifted storage conversions)
   double *partials = nullptr;     // per-block sums of the step kernel
   int partials_cap = 0;
   InflowArgs *inflow_dev = nullptr; // ghost-plane table of the current call
@@ -359,8 +376,8 @@ KParams make_params(const lbrt_ctx *c, int mode) {
   if (d.moving_fluid) p.flags |= KF_MOVING;
   if (d.lambda_aniso == 0.0) p.flags |= KF_LAMZERO;
   if (c->nwq_zero) p.flags |= KF_NWQZERO;
-  if ((d.storage == LBRT_BF16 || d.storage == LBRT_FP16) && d.rounding == LBRT_ROUND_STOCHASTIC)
-    p.flags |= KF_STOCH;
+  if (is_reduced(d.storage) && d.rounding == LBRT_ROUND_STOCHASTIC) p.flags |= KF_STOCH;
+  p.e_off = e_offset(d.storage, d.ndir, p.ncell);
   p.dt = d.dt;  // time step in length units (c = 1)
   p.lam = d.lambda_aniso;
   return p;
@@ -547,7 +564,7 @@ int prepare_step(lbrt_ctx *c, void *I_a, void *I_b, const float *kappa_a, const 
   if (I_a == I_b) return fail(LBRT_E_INVAL, "I_a and I_b must be distinct (ping-pong)");
   const lbrt_desc &d = c->desc;
   const int64_t ncell = (int64_t)d.nx * d.ny * d.nz;
-  const size_t bytes = storage_bytes(d.storage) * (size_t)ncell * d.ndir;
+  const size_t bytes = (size_t)state_bytes(d.storage, d.ndir, ncell);
   const char *a = static_cast<const char *>(I_a), *b = static_cast<const char *>(I_b);
   if (a < b + bytes && b < a + bytes) return fail(LBRT_E_INVAL, "I_a and I_b overlap");
   if (!kappa_a || !kappa_s || !eta) return fail(LBRT_E_INVAL, "kappa_a, kappa_s, eta required");
@@ -657,7 +674,7 @@ int lbrt_validate(const lbrt_desc *d) {
       return fail(LBRT_E_INVAL, "bc[%d] = %d is not a boundary kind", f, d->bc[f]);
   if (!is_periodic_pair_ok(d->bc))
     return fail(LBRT_E_INVAL, "periodic boundaries must be set on both faces of an axis");
-  if (d->storage < LBRT_FP32 || d->storage > LBRT_FP16)
+  if (d->storage < LBRT_FP32 || d->storage > LBRT_FP16_SHIFTED)
     return fail(LBRT_E_INVAL, "storage = %d is not a storage type", d->storage);
   if (d->collision < LBRT_COLL_IMPLICIT || d->collision > LBRT_COLL_LAMBDA)
     return fail(LBRT_E_INVAL, "collision = %d is not a collision kind", d->collision);
@@ -711,7 +728,7 @@ int lbrt_init(const lbrt_desc *d, lbrt_ctx **out) {
   c->dirs.assign(d->dirs, d->dirs + 3 * d->ndir);
   c->weights.assign(d->weights, d->weights + d->ndir);
   c->scales.resize(d->ndir);
-  const bool reduced = d->storage == LBRT_BF16 || d->storage == LBRT_FP16;
+  const bool reduced = is_reduced(d->storage);
   for (int i = 0; i < d->ndir; ++i)
     c->scales[i] = reduced ? (d->scale ? d->scale[i] : std::fabs(d->weights[i])) : 1.0;
   c->bucket = bucket_for(d->ndir);
@@ -817,13 +834,17 @@ int lbrt_init(const lbrt_desc *d, lbrt_ctx **out) {
   if (e == hipSuccess)
     e = hipMemcpy(c->scales_dev, c->scales.data(), sizeof(double) * d->ndir,
                   hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&c->weights_dev, sizeof(double) * d->ndir);
+  if (e == hipSuccess)
+    e = hipMemcpy(c->weights_dev, c->weights.data(), sizeof(double) * d->ndir,
+                  hipMemcpyHostToDevice);
   {
     std::vector<CoupDir> cd(d->ndir);
     for (int i = 0; i < d->ndir; ++i) {
       const double *n = &c->dirs[3 * i];
       cd[i] = CoupDir{{n[0], n[1], n[2]},
                       {n[0] * n[0], n[0] * n[1], n[0] * n[2], n[1] * n[1], n[1] * n[2], n[2] * n[2]},
-                      c->scales[i]};
+                      c->scales[i], c->weights[i]};
     }
     if (e == hipSuccess) e = hipMalloc(&c->coup_dev, sizeof(CoupDir) * d->ndir);
     if (e == hipSuccess)
@@ -881,6 +902,7 @@ void lbrt_destroy(lbrt_ctx *c) {
   if (c->pair_tab_dev) (void)hipFree(c->pair_tab_dev);
   if (c->pair_coll_dev) (void)hipFree(c->pair_coll_dev);
   if (c->scales_dev) (void)hipFree(c->scales_dev);
+  if (c->weights_dev) (void)hipFree(c->weights_dev);
   if (c->coup_dev) (void)hipFree(c->coup_dev);
   if (c->partials) (void)hipFree(c->partials);
   if (c->inflow_dev) (void)hipFree(c->inflow_dev);
@@ -1007,6 +1029,7 @@ int lbrt_coupling(lbrt_ctx *c, const void *I, const float *vel, const float *kap
   a.eta = eta;
   a.ks_factor = 1.0 - d.lambda_aniso / 9.0;
   a.ncell = (int64_t)d.nx * d.ny * d.nz;
+  a.e_off = e_offset(d.storage, d.ndir, a.ncell);
   a.ndir = d.ndir;
   hipError_t e = launch_coupling(d.storage, I, c->coup_dev, a, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "lbrt_coupling");
@@ -1017,20 +1040,34 @@ int lbrt_convert(lbrt_ctx *c, const void *src, int32_t src_storage, void *dst,
                  int32_t dst_storage, void *stream) {
   if (!c) return fail(LBRT_E_INVAL, "ctx is NULL");
   if (!src || !dst) return fail(LBRT_E_INVAL, "src and dst are required");
-  if (src_storage < LBRT_FP32 || src_storage > LBRT_FP16 || dst_storage < LBRT_FP32 ||
-      dst_storage > LBRT_FP16)
+  if (src_storage < LBRT_FP32 || src_storage > LBRT_FP16_SHIFTED ||
+      dst_storage < LBRT_FP32 || dst_storage > LBRT_FP16_SHIFTED)
     return fail(LBRT_E_INVAL, "bad storage type");
+  if (is_shifted(src_storage) && is_shifted(dst_storage))
+    return fail(LBRT_E_UNSUPPORTED, "shifted to shifted: convert through FP32");
   const lbrt_desc &d = c->desc;
   const int64_t ncell = (int64_t)d.nx * d.ny * d.nz;
-  const size_t sb = storage_bytes(src_storage) * (size_t)ncell * d.ndir;
-  const size_t db = storage_bytes(dst_storage) * (size_t)ncell * d.ndir;
+  const size_t sb = (size_t)state_bytes(src_storage, d.ndir, ncell);
+  const size_t db = (size_t)state_bytes(dst_storage, d.ndir, ncell);
   const char *a = static_cast<const char *>(src), *b = static_cast<const char *>(dst);
   if (a < b + db && b < a + sb) return fail(LBRT_E_INVAL, "src and dst overlap");
-  // The context's scales apply to the reduced (BF16/FP16) endpoint.
-  hipError_t e = launch_convert(src, src_storage, dst, dst_storage, c->scales_dev, d.ndir, ncell,
+  // The context's scales apply to the reduced (BF16/FP16, shifted) endpoint.
+  const int sh = is_shifted(src_storage) ? src_storage : dst_storage;
+  hipError_t e = launch_convert(src, src_storage, dst, dst_storage, c->scales_dev,
+                                c->weights_dev, d.ndir, ncell, e_offset(sh, d.ndir, ncell),
                                 static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "lbrt_convert");
   return LBRT_OK;
+}
+
+int64_t lbrt_state_bytes(int32_t storage, int32_t ndir, int64_t ncell) {
+  if (storage < LBRT_FP32 || storage > LBRT_FP16_SHIFTED || ndir < 0 || ncell < 0) return -1;
+  return state_bytes(storage, ndir, ncell);
+}
+
+int64_t lbrt_state_e_offset(int32_t storage, int32_t ndir, int64_t ncell) {
+  if (storage < LBRT_FP32 || storage > LBRT_FP16_SHIFTED || ndir < 0 || ncell < 0) return -1;
+  return e_offset(storage, ndir, ncell);
 }
 
 int lbrt_stream_copy(const void *src, void *dst, int64_t bytes, void *stream) {

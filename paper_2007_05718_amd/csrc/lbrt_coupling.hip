@@ -40,8 +40,13 @@ coupling_kernel(const S *__restrict__ I, const CoupDir *__restrict__ dir, CoupAr
   double m[10];
 #pragma unroll
   for (int k = 0; k < 10; ++k) m[k] = 0.0;
+  double Ec = 0.0;   // equilibrium-shifted storage: the cell's stored E
+  if constexpr (Tr::kShifted)
+    Ec = (double)reinterpret_cast<const float *>(reinterpret_cast<const char *>(I) +
+                                                 a.e_off)[cell];
   auto add = [&](const CoupDir &d, double v) {
     if (Tr::kReduced) v *= d.s;
+    if constexpr (Tr::kShifted) v = fma(d.w, Ec, v);
     m[0] += v;
 #pragma unroll
     for (int k = 0; k < 3; ++k) m[1 + k] = fma(d.n[k], v, m[1 + k]);
@@ -124,7 +129,9 @@ hipError_t launch_coupling(int storage, const void *I, const CoupDir *dir, const
     case LBRT_FP32: launch_as<float, float>(I, dir, a, s); break;
     case LBRT_FP64: launch_as<double, double>(I, dir, a, s); break;
     case LBRT_BF16: launch_as<bf16_t, float>(I, dir, a, s); break;
-    default: launch_as<f16_t, float>(I, dir, a, s); break;
+    case LBRT_FP16: launch_as<f16_t, float>(I, dir, a, s); break;
+    case LBRT_BF16_SHIFTED: launch_as<bf16s_t, float>(I, dir, a, s); break;
+    default: launch_as<f16s_t, float>(I, dir, a, s); break;
   }
   return hipGetLastError();
 }

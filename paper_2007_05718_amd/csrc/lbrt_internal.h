@@ -11,6 +11,10 @@ namespace lbrt {
 // 16-bit storage wrappers (bit patterns; conversions live in the kernels).
 struct bf16_t { uint16_t u; };
 struct f16_t { uint16_t u; };
+// Equilibrium-shifted 16-bit storage: the deviation (I_i - w_i E) / s_i, with
+// the cell's E in an FP32 array after the populations (KParams::e_off).
+struct bf16s_t { uint16_t u; };
+struct f16s_t { uint16_t u; };
 
 // Per-direction constants, in processing order (antipodal pairs adjacent
 // when the rule is centrally symmetric).  Axes where n^a == 0 get shift 0,
@@ -160,6 +164,8 @@ struct KParams {
   // ranges.
   int32_t pair;
   int32_t pair_x0, pair_xend;
+  // equilibrium-shifted storage: byte offset of a state's FP32 E array
+  int64_t e_off;
   const PairTab *pair_tab;     // the pair kernel's slot records (nb of each)
   const PairColl *pair_coll;
   int32_t periodic[3];         // per axis x, y, z
@@ -249,8 +255,9 @@ struct CoupDir {
   double n[3];
   double nn[6];
   double s;
+  double w;   // quadrature weight (equilibrium-shifted storage: I_i = w_i E + s_i d_i)
 };
-static_assert(sizeof(CoupDir) == 80, "CoupDir layout");
+static_assert(sizeof(CoupDir) == 88, "CoupDir layout");
 
 // Outputs (any may be null), the fluid inputs and the sizes of a coupling pass.
 struct CoupArgs {
@@ -258,12 +265,14 @@ struct CoupArgs {
   const float *vel, *kappa_a, *kappa_s, *eta;
   double ks_factor;   // 1 - lambda / 9: k_s = k_0 - k_1 / 3 with k_1 = lambda k_0 / 3
   int64_t ncell;
+  int64_t e_off;      // equilibrium-shifted storage: byte offset of the state's E
   int ndir;
 };
 hipError_t launch_coupling(int storage, const void *I, const CoupDir *dir, const CoupArgs &a,
                            hipStream_t s);
 hipError_t launch_convert(const void *src, int src_storage, void *dst, int dst_storage,
-                          const double *scales_dev, int ndir, int64_t ncell, hipStream_t s);
+                          const double *scales_dev, const double *weights_dev, int ndir,
+                          int64_t ncell, int64_t e_off, hipStream_t s);
 // Reduces the step kernel's per-block partials (nblocks rows of
 // kStepPartials) into diag in a fixed order: sums of E and E* replace diag[0]
 // and diag[8]; fluxes are added to diag[1..7] (replaced when first_step).

@@ -1,0 +1,7 @@
+// Fused stream-collide kernel: BF16 equilibrium-shifted storage, 112-slot
+// bucket, static fluid.
+#include "lbrt_step_kernel.h"
+
+namespace lbrt {
+StepLauncher launcher_bf16s_112_static() { return &launch_step<bf16s_t, 112, false>; }
+}  // namespace lbrt

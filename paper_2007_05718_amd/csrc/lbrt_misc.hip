@@ -9,7 +9,7 @@ namespace lbrt {
 template <typename S>
 __global__ void __launch_bounds__(kBlock)
 moments_kernel(const S *__restrict__ I, const DirTab<typename StoreTraits<S>::T> *__restrict__ tab,
-               int ndir, int64_t ncell, typename StoreTraits<S>::T *__restrict__ E,
+               int ndir, int64_t ncell, int64_t e_off, typename StoreTraits<S>::T *__restrict__ E,
                typename StoreTraits<S>::T *__restrict__ F) {
   using Tr = StoreTraits<S>;
   using T = typename Tr::T;
@@ -22,6 +22,9 @@ moments_kernel(const S *__restrict__ I, const DirTab<typename StoreTraits<S>::T>
     const DirTab<T> &d = tab[i];
     T v = Tr::ld(I + (int64_t)d.plane * ncell + cell);
     if (Tr::kReduced) v *= d.scale;
+    if constexpr (Tr::kShifted)   // I_i = w_i E + s_i d_i
+      v = fma(d.w, (T)reinterpret_cast<const float *>(
+                       reinterpret_cast<const char *>(I) + e_off)[cell], v);
     const double vd = (double)v;
     e += vd;
     f0 = fma((double)d.n[0], vd, f0);
@@ -50,9 +53,14 @@ __device__ inline void store_phys(void *p, int64_t i, double v, double inv_s) {
   Tr::st(static_cast<S *>(p) + i, Tr::kReduced ? (T)(v * inv_s) : (T)v);
 }
 
+// Conversion of a state between storage types, one element per thread (for
+// an equilibrium-shifted source, I_i = w_i E + s_i d_i with the cell's E at
+// byte e_off of the source; a shifted destination is written by
+// shift_encode_kernel instead).
 __global__ void __launch_bounds__(kBlock)
 convert_kernel(const void *src, int src_storage, void *dst, int dst_storage,
-               const double *__restrict__ scales, int ndir, int64_t ncell) {
+               const double *__restrict__ scales, const double *__restrict__ weights, int ndir,
+               int64_t ncell, int64_t e_off) {
   const int64_t total = ncell * ndir;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * kBlock) {
@@ -62,7 +70,15 @@ convert_kernel(const void *src, int src_storage, void *dst, int dst_storage,
       case LBRT_FP32: v = load_phys<float>(src, i, s); break;
       case LBRT_FP64: v = load_phys<double>(src, i, s); break;
       case LBRT_BF16: v = load_phys<bf16_t>(src, i, s); break;
-      default: v = load_phys<f16_t>(src, i, s); break;
+      case LBRT_FP16: v = load_phys<f16_t>(src, i, s); break;
+      default: {
+        const double E = (double)reinterpret_cast<const float *>(
+            static_cast<const char *>(src) + e_off)[i % ncell];
+        v = src_storage == LBRT_BF16_SHIFTED ? load_phys<bf16s_t>(src, i, s)
+                                             : load_phys<f16s_t>(src, i, s);
+        v = fma(weights[i / ncell], E, v);
+        break;
+      }
     }
     switch (dst_storage) {
       case LBRT_FP32: store_phys<float>(dst, i, v, 1.0 / s); break;
@@ -71,6 +87,35 @@ convert_kernel(const void *src, int src_storage, void *dst, int dst_storage,
       default: store_phys<f16_t>(dst, i, v, 1.0 / s); break;
     }
   }
+}
+
+// An equilibrium-shifted state from any other: per cell (one thread), the
+// FP64 sum of its populations in direction order, rounded to FP32, is the
+// cell's E (stored at byte e_off of dst), and each population is stored as
+// (I_i - w_i E) / s_i, rounded to nearest.
+template <typename D>
+__global__ void __launch_bounds__(kBlock)
+shift_encode_kernel(const void *src, int src_storage, void *dst,
+                    const double *__restrict__ scales, const double *__restrict__ weights,
+                    int ndir, int64_t ncell, int64_t e_off) {
+  const int64_t cell = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (cell >= ncell) return;
+  auto phys = [&](int i) -> double {
+    const int64_t k = (int64_t)i * ncell + cell;
+    switch (src_storage) {
+      case LBRT_FP32: return load_phys<float>(src, k, 1.0);
+      case LBRT_FP64: return load_phys<double>(src, k, 1.0);
+      case LBRT_BF16: return load_phys<bf16_t>(src, k, scales[i]);
+      default: return load_phys<f16_t>(src, k, scales[i]);
+    }
+  };
+  double e = 0.0;
+  for (int i = 0; i < ndir; ++i) e += phys(i);
+  const float E = (float)e;
+  reinterpret_cast<float *>(static_cast<char *>(dst) + e_off)[cell] = E;
+  for (int i = 0; i < ndir; ++i)
+    store_phys<D>(dst, (int64_t)i * ncell + cell, phys(i) - weights[i] * (double)E,
+                  1.0 / scales[i]);
 }
 
 // Fixed-order reduction of the step kernel's per-block partials into diag:
@@ -155,34 +200,58 @@ hipError_t launch_moments(int storage, const void *I, const void *tab, const KPa
     case LBRT_FP32:
       hipLaunchKernelGGL(moments_kernel<float>, dim3(nb), dim3(kBlock), 0, s,
                          static_cast<const float *>(I), static_cast<const DirTab<float> *>(tab),
-                         p.ndir, p.ncell, static_cast<float *>(E), static_cast<float *>(F));
+                         p.ndir, p.ncell, p.e_off, static_cast<float *>(E), static_cast<float *>(F));
       break;
     case LBRT_FP64:
       hipLaunchKernelGGL(moments_kernel<double>, dim3(nb), dim3(kBlock), 0, s,
                          static_cast<const double *>(I), static_cast<const DirTab<double> *>(tab),
-                         p.ndir, p.ncell, static_cast<double *>(E), static_cast<double *>(F));
+                         p.ndir, p.ncell, p.e_off, static_cast<double *>(E), static_cast<double *>(F));
       break;
     case LBRT_BF16:
       hipLaunchKernelGGL(moments_kernel<bf16_t>, dim3(nb), dim3(kBlock), 0, s,
                          static_cast<const bf16_t *>(I), static_cast<const DirTab<float> *>(tab),
-                         p.ndir, p.ncell, static_cast<float *>(E), static_cast<float *>(F));
+                         p.ndir, p.ncell, p.e_off, static_cast<float *>(E), static_cast<float *>(F));
       break;
-    default:
+    case LBRT_FP16:
       hipLaunchKernelGGL(moments_kernel<f16_t>, dim3(nb), dim3(kBlock), 0, s,
                          static_cast<const f16_t *>(I), static_cast<const DirTab<float> *>(tab),
-                         p.ndir, p.ncell, static_cast<float *>(E), static_cast<float *>(F));
+                         p.ndir, p.ncell, p.e_off, static_cast<float *>(E),
+                         static_cast<float *>(F));
+      break;
+    case LBRT_BF16_SHIFTED:
+      hipLaunchKernelGGL(moments_kernel<bf16s_t>, dim3(nb), dim3(kBlock), 0, s,
+                         static_cast<const bf16s_t *>(I), static_cast<const DirTab<float> *>(tab),
+                         p.ndir, p.ncell, p.e_off, static_cast<float *>(E),
+                         static_cast<float *>(F));
+      break;
+    default:
+      hipLaunchKernelGGL(moments_kernel<f16s_t>, dim3(nb), dim3(kBlock), 0, s,
+                         static_cast<const f16s_t *>(I), static_cast<const DirTab<float> *>(tab),
+                         p.ndir, p.ncell, p.e_off, static_cast<float *>(E),
+                         static_cast<float *>(F));
       break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_convert(const void *src, int src_storage, void *dst, int dst_storage,
-                          const double *scales_dev, int ndir, int64_t ncell, hipStream_t s) {
+                          const double *scales_dev, const double *weights_dev, int ndir,
+                          int64_t ncell, int64_t e_off, hipStream_t s) {
+  if (dst_storage == LBRT_BF16_SHIFTED || dst_storage == LBRT_FP16_SHIFTED) {
+    const unsigned nb = (unsigned)((ncell + kBlock - 1) / kBlock);
+    if (dst_storage == LBRT_BF16_SHIFTED)
+      hipLaunchKernelGGL(shift_encode_kernel<bf16s_t>, dim3(nb), dim3(kBlock), 0, s, src,
+                         src_storage, dst, scales_dev, weights_dev, ndir, ncell, e_off);
+    else
+      hipLaunchKernelGGL(shift_encode_kernel<f16s_t>, dim3(nb), dim3(kBlock), 0, s, src,
+                         src_storage, dst, scales_dev, weights_dev, ndir, ncell, e_off);
+    return hipGetLastError();
+  }
   const int64_t total = ncell * ndir;
   int64_t nb = (total + kBlock - 1) / kBlock;
   if (nb > 65536) nb = 65536;
   hipLaunchKernelGGL(convert_kernel, dim3((unsigned)nb), dim3(kBlock), 0, s, src, src_storage,
-                     dst, dst_storage, scales_dev, ndir, ncell);
+                     dst, dst_storage, scales_dev, weights_dev, ndir, ncell, e_off);
   return hipGetLastError();
 }
 
@@ -222,9 +291,19 @@ hipError_t launch_zface(int storage, const void *I, const void *tab, const KPara
                          static_cast<const bf16_t *>(I), static_cast<const DirTab<float> *>(tab),
                          p, inflow, partials);
       break;
-    default:
+    case LBRT_FP16:
       hipLaunchKernelGGL(zface_kernel<f16_t>, grid, dim3(kBlock), 0, s,
                          static_cast<const f16_t *>(I), static_cast<const DirTab<float> *>(tab),
+                         p, inflow, partials);
+      break;
+    case LBRT_BF16_SHIFTED:
+      hipLaunchKernelGGL(zface_kernel<bf16s_t>, grid, dim3(kBlock), 0, s,
+                         static_cast<const bf16s_t *>(I), static_cast<const DirTab<float> *>(tab),
+                         p, inflow, partials);
+      break;
+    default:
+      hipLaunchKernelGGL(zface_kernel<f16s_t>, grid, dim3(kBlock), 0, s,
+                         static_cast<const f16s_t *>(I), static_cast<const DirTab<float> *>(tab),
                          p, inflow, partials);
       break;
   }

@@ -123,7 +123,7 @@ template <> struct PairIO<f16_t> : PairIO16<f16_t> {
 // 112-slot buckets.
 template <typename S, int NB, bool MOVING>
 constexpr bool pair_kernel_exists() {
-  return !MOVING && sizeof(S) == 2 && (NB == 56 || NB == 112);
+  return !MOVING && sizeof(S) == 2 && !StoreTraits<S>::kShifted && (NB == 56 || NB == 112);
 }
 
 // Slots whose four row loads (4 VGPRs) are in flight ahead of the slot being

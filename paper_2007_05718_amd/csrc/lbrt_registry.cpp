@@ -33,6 +33,10 @@ StepLauncher launcher_f16_56_moving();
 StepLauncher launcher_f16_112_static();
 StepLauncher launcher_f16_152_static();
 StepLauncher launcher_f16_152_moving();
+StepLauncher launcher_bf16s_56_static();
+StepLauncher launcher_bf16s_112_static();
+StepLauncher launcher_f16s_56_static();
+StepLauncher launcher_f16s_112_static();
 StepLauncher launcher_f32_200_static();
 StepLauncher launcher_f32_200_moving();
 StepLauncher launcher_bf16_200_static();
@@ -75,6 +79,10 @@ StepLauncher step_launcher(int storage, int bucket_index, bool moving) {
   if (storage == LBRT_FP16 && nb == 112 && moving == false) return launcher_f16_112_static();
   if (storage == LBRT_FP16 && nb == 152 && moving == false) return launcher_f16_152_static();
   if (storage == LBRT_FP16 && nb == 152 && moving == true) return launcher_f16_152_moving();
+  if (storage == LBRT_BF16_SHIFTED && nb == 56 && moving == false) return launcher_bf16s_56_static();
+  if (storage == LBRT_BF16_SHIFTED && nb == 112 && moving == false) return launcher_bf16s_112_static();
+  if (storage == LBRT_FP16_SHIFTED && nb == 56 && moving == false) return launcher_f16s_56_static();
+  if (storage == LBRT_FP16_SHIFTED && nb == 112 && moving == false) return launcher_f16s_112_static();
   if (storage == LBRT_FP32 && nb == 200 && moving == false) return launcher_f32_200_static();
   if (storage == LBRT_FP32 && nb == 200 && moving == true) return launcher_f32_200_moving();
   if (storage == LBRT_BF16 && nb == 200 && moving == false) return launcher_bf16_200_static();

@@ -53,6 +53,7 @@ template <typename S> struct StoreTraits;
 template <> struct StoreTraits<float> {
   using T = float;
   static constexpr bool kReduced = false;
+  static constexpr bool kShifted = false;
   __device__ static T ld(const float *p) { return *p; }
   __device__ static void st(float *p, T v) { __builtin_nontemporal_store(v, p); }
 };
@@ -60,6 +61,7 @@ template <> struct StoreTraits<float> {
 template <> struct StoreTraits<double> {
   using T = double;
   static constexpr bool kReduced = false;
+  static constexpr bool kShifted = false;
   __device__ static T ld(const double *p) { return *p; }
   __device__ static void st(double *p, T v) { __builtin_nontemporal_store(v, p); }
 };
@@ -74,6 +76,7 @@ __device__ inline uint16_t f32_to_bf16_rne(float f) {
 template <> struct StoreTraits<bf16_t> {
   using T = float;
   static constexpr bool kReduced = true;
+  static constexpr bool kShifted = false;
   __device__ static T ld(const bf16_t *p) {
     return __uint_as_float((uint32_t)(*reinterpret_cast<const uint16_t *>(p)) << 16);
   }
@@ -85,6 +88,7 @@ template <> struct StoreTraits<bf16_t> {
 template <> struct StoreTraits<f16_t> {
   using T = float;
   static constexpr bool kReduced = true;
+  static constexpr bool kShifted = false;
   __device__ static T ld(const f16_t *p) {
     return (float)(*reinterpret_cast<const _Float16 *>(p));
   }
@@ -92,6 +96,23 @@ template <> struct StoreTraits<f16_t> {
     __builtin_nontemporal_store((_Float16)v, reinterpret_cast<_Float16 *>(p));
   }
 };
+
+// Equilibrium-shifted 16-bit storage: the stored value is the deviation
+// (I_i - w_i E) / s_i from the cell's isotropic equilibrium, E in FP32
+// beside it.  In an optically thick cell I_i is close to w_i E, and the
+// deviation (about 3 w_i n_i.F) keeps F to the format's relative precision
+// where plain 16-bit storage rounds it away with I_i.  The pull is linear,
+// so the streamed population is w_i E~_i + s_i d*_i, E~_i being E pulled
+// along direction i (the same trilinear weights).
+template <typename B, typename S> struct ShiftedTraits {
+  using T = float;
+  static constexpr bool kReduced = true;
+  static constexpr bool kShifted = true;
+  __device__ static T ld(const S *p) { return StoreTraits<B>::ld(reinterpret_cast<const B *>(p)); }
+  __device__ static void st(S *p, T v) { StoreTraits<B>::st(reinterpret_cast<B *>(p), v); }
+};
+template <> struct StoreTraits<bf16s_t> : ShiftedTraits<bf16_t, bf16s_t> {};
+template <> struct StoreTraits<f16s_t> : ShiftedTraits<f16_t, f16s_t> {};
 
 // ---------------------------------------------------------------------------
 // Stochastic rounding of 16-bit storage.  Round-to-nearest loses any
@@ -130,6 +151,12 @@ template <> __device__ __forceinline__ uint16_t to16_sr<bf16_t>(float v, uint32_
 template <> __device__ __forceinline__ uint16_t to16_sr<f16_t>(float v, uint32_t r) {
   const f16x2 h = __builtin_amdgcn_cvt_sr_f16_f32(f16x2{0, 0}, v, r, false);
   return __builtin_bit_cast(uint16_t, h.x);
+}
+template <> __device__ __forceinline__ uint16_t to16_sr<bf16s_t>(float v, uint32_t r) {
+  return to16_sr<bf16_t>(v, r);
+}
+template <> __device__ __forceinline__ uint16_t to16_sr<f16s_t>(float v, uint32_t r) {
+  return to16_sr<f16_t>(v, r);
 }
 
 // Store of a 16-bit population with stochastic rounding (random bits r).
@@ -376,6 +403,33 @@ checked_P(const DirTab<typename StoreTraits<S>::T> &d, const S *__restrict__ pl,
   return interp4(d, v[0], v[1], v[2], v[3]);
 }
 
+// Equilibrium-shifted storage: the cell energy E of plane zl (FP32, [y][x])
+// pulled with the same four taps and weights as checked_P.  A tap outside the
+// box (after the periodic wrap) is a ghost: a ghost population enters whole
+// through the deviation part, so its E part is 0.  `own` gets the unshifted
+// tap.
+template <typename T>
+__device__ __forceinline__ T checked_PE(const DirTab<T> &d, const float *__restrict__ pl, int x,
+                                        int y, bool valid, int nx, int ny, int perx, int pery,
+                                        T &own) {
+  T v[4];
+  bool inb[4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    int cx = x - (b & 1) * d.s[0];
+    int cy = y - (b >> 1) * d.s[1];
+    if (perx) cx = wrap(cx, nx);
+    if (pery) cy = wrap(cy, ny);
+    inb[b] = valid && (unsigned)cx < (unsigned)nx && (unsigned)cy < (unsigned)ny;
+    v[b] = (T)pl[inb[b] ? (int64_t)cy * nx + cx : 0];
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+    if (!inb[b]) v[b] = T(0);
+  own = v[0];
+  return interp4(d, v[0], v[1], v[2], v[3]);
+}
+
 // Plane value of a plane outside the box in z (non-periodic): taps inside the
 // box in x and y read the z-face inflow ghost plane ([y][x] layout); all other
 // taps are vacuum.
@@ -588,6 +642,12 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
   constexpr int SZ = (int)sizeof(S);
   constexpr int M = NB / NW;
   static_assert(NB % NW == 0, "direction slots must split evenly over the waves");
+  // Equilibrium-shifted storage: the states' FP32 E arrays (byte offset
+  // e_off in each state buffer); E element offsets are twice the 16-bit ones.
+  constexpr bool SH = Tr::kShifted;
+  static_assert(!(SH && MOVING), "shifted storage: static fluid only");
+  const char *const ein_bytes = reinterpret_cast<const char *>(Iin) + (SH ? p.e_off : 0);
+  char *const eout_bytes = reinterpret_cast<char *>(Iout) + (SH ? p.e_off : 0);
   static_assert(NB / NW <= 32, "a wave's slots must fit a 32-bit mask");
 
   const int nx = p.nx, ny = p.ny, nz = p.nz;
@@ -643,17 +703,24 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
   // general rules: a plane outside the box in z is the z ghost plane (or
   // vacuum), otherwise each tap is checked.  With `book` (zl is one of this
   // block's planes) the own value is booked as x/y-face outflux.
-  auto general_P = [&](const DirTab<T> &d, int slot, int zl, bool book) -> T {
+  // Shifted storage: PE gets E pulled along the slot (0 for a ghost plane).
+  auto general_P = [&](const DirTab<T> &d, int slot, int zl, bool book, T &PE) -> T {
+    PE = T(0);
     if ((unsigned)zl >= (unsigned)nz)
       return ghost_P<S>(d, inflow->ghost[slot][2], x, y, valid, nx, ny, perx, pery);
     T own;
     const S *pl = Iin + (d.plane_off / SZ) + (int64_t)zl * pc;
     const T P = checked_P<S>(d, pl, x, y, valid, nx, ny, perx, pery, inflow->ghost[slot][1], zl,
                              own);
+    T ownE = T(0);
+    if constexpr (SH)
+      PE = checked_PE<T>(d, reinterpret_cast<const float *>(ein_bytes) + (int64_t)zl * pc, x, y,
+                         valid, nx, ny, perx, pery, ownE);
     if (diag && book && face_tile && valid) {
       T fz = T(0);
-      book_outflux(d, Tr::kReduced ? own * d.scale : own, lox, hix, loy, hiy, false, false, fx, fy,
-                   fz, fz);
+      T ownp = Tr::kReduced ? own * d.scale : own;
+      if constexpr (SH) ownp = fma(d.w, ownE, ownp);
+      book_outflux(d, ownp, lox, hix, loy, hiy, false, false, fx, fy, fz, fz);
     }
     return P;
   };
@@ -674,6 +741,18 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
     v[1] = ldo<S>(r0, ax);
     v[2] = ldo<S>(r1, a0);
     v[3] = ldo<S>(r1, ax);
+  };
+  // Shifted storage: the same four taps of the E array at plane byte `plane`
+  // (FP32: every byte offset doubles).
+  auto load4E = [&](const DirTab<T> &d, const char *plane, T (&v)[4]) {
+    const float *r0 = reinterpret_cast<const float *>(plane);
+    const float *r1 = reinterpret_cast<const float *>(plane + 2 * d.row_off);
+    const uint32_t a0 = 2u * o0;
+    const uint32_t ax = a0 + ((2u * dxp) & d.mxp) + ((2u * dxm) & d.mxm);
+    v[0] = (T)ldo<float>(r0, a0);
+    v[1] = (T)ldo<float>(r0, ax);
+    v[2] = (T)ldo<float>(r1, a0);
+    v[3] = (T)ldo<float>(r1, ax);
   };
   // factor of the x-shifted taps of slot d for this lane (0 at a ghost)
   auto xkeep = [&](const DirTab<T> &d) {
@@ -708,22 +787,34 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
   // for sz < 0; nothing for sz == 0).  On the main path a plane outside the
   // box is vacuum (its clamped loads are weighted by 0).
   T carry[M];
+  T carryE[M];   // shifted storage: the carried plane of E pulled along the slot
   {
     auto pro = [&]<int J>() {
       const DirTab<T> &d = tb[J];
       carry[J] = T(0);
+      carryE[J] = T(0);
       if (d.s[2] != 0) {
         int zl = d.s[2] > 0 ? zb - 1 : zb;
         if (perz) zl = wrap(zl, nz);
         if constexpr (MAIN) {
           T v[4];
           const bool in = (unsigned)zl < (unsigned)nz;
-          load4(d, in_bytes + (int64_t)min(max(zl, 0), nz - 1) * pc * SZ, v);
+          const int zc = min(max(zl, 0), nz - 1);
+          load4(d, in_bytes + (int64_t)zc * pc * SZ, v);
           const T k1 = xkeep(d);
           carry[J] = (in ? T(1) : T(0)) * interp4(d, v[0], v[1] * k1, v[2], v[3] * k1);
-          if (diag && d.s[2] < 0) fx = fma(fma(d.cxp, xop, d.cxm * xom) * d.dxs, v[0], fx);
+          const T ko = fma(d.cxp, xop, d.cxm * xom);
+          if (diag && d.s[2] < 0) fx = fma(ko * d.dxs, v[0], fx);
+          if constexpr (SH) {
+            T e[4];
+            load4E(d, ein_bytes + (int64_t)zc * pc * 4, e);
+            carryE[J] = (in ? T(1) : T(0)) * interp4(d, e[0], e[1] * k1, e[2], e[3] * k1);
+            if (diag && d.s[2] < 0) fx = fma(ko * (d.delta[0] * d.w), e[0], fx);
+          }
         } else {
-          carry[J] = general_P(d, q * M + J, zl, d.s[2] < 0);
+          T PE;
+          carry[J] = general_P(d, q * M + J, zl, d.s[2] < 0, PE);
+          carryE[J] = PE;
         }
       }
     };
@@ -744,10 +835,16 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
   // before the collision's stores.
   constexpr int D = pf_depth<S, MOVING>(M);
   T pf[M][4];
+  T pfE[M][4];   // shifted storage: the slots' E taps, in flight with pf
   auto issue_first = [&](int zn) {
     const char *const p0 = in_bytes + (int64_t)zn * pc * SZ;
     const char *const p1 = in_bytes + plane_above(zn) * SZ;
-    auto one = [&]<int J>() { load4(tb[J], tb[J].dzn_a ? p1 : p0, pf[J]); };
+    const char *const e0 = ein_bytes + (int64_t)zn * pc * 4;
+    const char *const e1 = ein_bytes + plane_above(zn) * 4;
+    auto one = [&]<int J>() {
+      load4(tb[J], tb[J].dzn_a ? p1 : p0, pf[J]);
+      if constexpr (SH) load4E(tb[J], tb[J].dzn_a ? e1 : e0, pfE[J]);
+    };
     unroll<0, D>(one);
   };
   if constexpr (MAIN)
@@ -800,6 +897,8 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
       // plane above a non-periodic box is clamped into it and weighted 0
       const char *const p0 = in_bytes + cz * SZ;
       const char *const p1 = in_bytes + plane_above(z) * SZ;
+      const char *const e0 = ein_bytes + cz * 4;
+      const char *const e1 = ein_bytes + plane_above(z) * 4;
       // the plane above a non-periodic box is vacuum: weight 0
       const int gh = (!perz && z + 1 >= nz) ? 1 : 0;
       // the plane above the last plane of the range belongs to the next block
@@ -812,15 +911,19 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
       // J + D before interpolating its own.
       auto slot = [&]<int J, bool FACE>() {
         const DirTab<T> &d = tb[J];
-        if constexpr (J + D < M) load4(tb[J + D], tb[J + D].dzn_a ? p1 : p0, pf[J + D]);
+        if constexpr (J + D < M) {
+          load4(tb[J + D], tb[J + D].dzn_a ? p1 : p0, pf[J + D]);
+          if constexpr (SH) load4E(tb[J + D], tb[J + D].dzn_a ? e1 : e0, pfE[J + D]);
+        }
         const T(&cur)[4] = pf[J];
         T c1 = cur[1], c3 = cur[3];
+        T k1 = T(1), ko = T(0);
         if constexpr (FACE) {
-          const T k1 = xkeep(d);
+          k1 = xkeep(d);
           c1 *= k1;
           c3 *= k1;
           // the plane above the range belongs to the next block
-          const T ko = fma(d.cxp, xop, d.cxm * xom);
+          ko = fma(d.cxp, xop, d.cxm * xom);
           const T dxs = zero_if(d.dxs, d.dzn & lastz);
           fx = fma(ko * dxs, cur[0], fx);
         }
@@ -829,6 +932,14 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
         const T wn = zero_if(d.wz_new, d.dzn & gh);
         T sv = fma(d.wz_old, carry[J], wn * Pn);
         if (Tr::kReduced) sv *= d.scale;
+        if constexpr (SH) {
+          const T(&ce)[4] = pfE[J];
+          const T PEn = interp4(d, ce[0], ce[1] * k1, ce[2], ce[3] * k1);
+          if constexpr (FACE)
+            fx = fma(ko * zero_if(d.delta[0] * d.w, d.dzn & lastz), ce[0], fx);
+          sv = fma(d.w, fma(d.wz_old, carryE[J], wn * PEn), sv);
+          carryE[J] = PEn;
+        }
         Is[J] = sv;
         carry[J] = Pn;
         accumulate<MOVING, J, M>(m, tb, Is, vx, vy, vz, dtWk);
@@ -842,9 +953,14 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
     } else {
       auto body = [&]<int J>() {
         const DirTab<T> &d = tb[J];
-        const T Pn = general_P(d, q * M + J, new_plane(d, z), own_plane(d, z));
+        T PEn;
+        const T Pn = general_P(d, q * M + J, new_plane(d, z), own_plane(d, z), PEn);
         T sv = fma(d.wz_old, carry[J], d.wz_new * Pn);
         if (Tr::kReduced) sv *= d.scale;
+        if constexpr (SH) {
+          sv = fma(d.w, fma(d.wz_old, carryE[J], d.wz_new * PEn), sv);
+          carryE[J] = PEn;
+        }
         Is[J] = valid ? sv : T(0);
         carry[J] = Pn;
         accumulate<MOVING, J, M>(m, tb, Is, vx, vy, vz, dtWk);
@@ -958,6 +1074,12 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
       issue_next();
       if (valid) {
         const bool lz = (p.flags & KF_LAMZERO) != 0;
+        // shifted storage stores the deviation from w_i E' (E' this
+        // plane's new E, stored beside it)
+        auto shift = [&](const DirTab<T> &d, T o) -> T {
+          if constexpr (SH) return (T)fma(-d.w, En, o);
+          return o;
+        };
         if (Tr::kReduced && (p.flags & KF_STOCH)) {
           const uint32_t gr = cell_hash((uint32_t)(cz + ocell) ^ p.seed);
 #pragma unroll
@@ -965,7 +1087,8 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
             const DirTab<T> &d = tbc[j];
             if (d.active)
               sto_sr<S>(outz + d.plane_off, ost,
-                        collide_one(d, c, alpha, be0, be1, be2, Is[j], lz) * d.inv_scale,
+                        shift(d, collide_one(d, c, alpha, be0, be1, be2, Is[j], lz)) *
+                            d.inv_scale,
                         gr ^ d.rnd);
           }
         } else if (lz) {
@@ -973,7 +1096,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
           for (int j = 0; j < M; ++j) {
             const DirTab<T> &d = tbc[j];
             if (d.active) {
-              T o = collide_one(d, c, alpha, be0, be1, be2, Is[j], true);
+              T o = shift(d, collide_one(d, c, alpha, be0, be1, be2, Is[j], true));
               if (Tr::kReduced) o *= d.inv_scale;
               sto<S>(outz + d.plane_off, ost, o);
             }
@@ -983,7 +1106,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
           for (int j = 0; j < M; ++j) {
             const DirTab<T> &d = tbc[j];
             if (d.active) {
-              T o = collide_one(d, c, alpha, be0, be1, be2, Is[j], false);
+              T o = shift(d, collide_one(d, c, alpha, be0, be1, be2, Is[j], false));
               if (Tr::kReduced) o *= d.inv_scale;
               sto<S>(outz + d.plane_off, ost, o);
             }
@@ -1049,6 +1172,11 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
       __syncthreads();
     }
 
+    if constexpr (SH) {
+      // the new state's E, part of the shifted state (wave 0)
+      if (q == 0 && valid)
+        *reinterpret_cast<float *>(eout_bytes + cz * 4 + opaque_lane(ocell * 4u)) = (float)En;
+    }
     if (q == 0 && valid) {
       if (p.flags & KF_WRITE_EF) {
         // at a uniform base plus the lane's (opaque) byte offset, as above
@@ -1165,6 +1293,10 @@ zface_kernel(const S *__restrict__ I, const DirTab<typename StoreTraits<S>::T> *
         // leaves through this face
         T own = Tr::ld(I + (d.plane_off / (int64_t)sizeof(S)) + (int64_t)z * pc + c);
         if (Tr::kReduced) own *= d.scale;
+        if constexpr (Tr::kShifted)
+          own = fma(d.w, (T)reinterpret_cast<const float *>(
+                             reinterpret_cast<const char *>(I) + p.e_off)[(int64_t)z * pc + c],
+                    own);
         T fx = T(0), fy = T(0), flo = T(0), fhi = T(0);
         book_outflux(d, own, lox, hix, loy, hiy, face == 0, face == 1, fx, fy, flo, fhi);
         out += flo + fhi;

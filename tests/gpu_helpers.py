@@ -37,6 +37,22 @@ def host_encoded_state(I0: np.ndarray, weights: np.ndarray, storage: int):
         h = torch.from_numpy(np.ascontiguousarray(I0, dtype=np.float32))
         return h.cuda(), h.double().numpy()
     s = np.abs(weights).reshape((-1,) + (1,) * (I0.ndim - 1))
+    if storage in (L.LBRT_BF16_SHIFTED, L.LBRT_FP16_SHIFTED):
+        # the deviation from w_i E, E = sum_i I_i rounded to FP32, stored
+        # beside it (layout of lbrt.h)
+        w = np.asarray(weights, dtype=np.float64).reshape(s.shape)
+        E = I0.sum(axis=0).astype(np.float32)
+        dev = (I0 - w * E.astype(np.float64)) / s
+        t16 = {L.LBRT_BF16_SHIFTED: torch.bfloat16, L.LBRT_FP16_SHIFTED: torch.float16}[storage]
+        q16 = torch.from_numpy(np.ascontiguousarray(dev, dtype=np.float32)).to(t16)
+        ndir, ncell = I0.shape[0], int(np.prod(I0.shape[1:]))
+        buf = torch.zeros(L.state_bytes(storage, ndir, ncell), dtype=torch.uint8)
+        nb16 = 2 * ndir * ncell
+        buf[:nb16] = q16.reshape(-1).view(torch.uint8)
+        off = L.state_e_offset(storage, ndir, ncell)
+        buf[off:off + 4 * ncell] = torch.from_numpy(E.reshape(-1)).view(torch.uint8)
+        eff = w * E.astype(np.float64) + q16.double().numpy() * s
+        return buf.cuda(), eff
     q = torch.from_numpy(np.ascontiguousarray(I0 / s, dtype=np.float32))
     q16 = q.to(pop_torch_dtype(storage))
     eff = q16.double().numpy() * s
@@ -102,7 +118,7 @@ def run_problem(prob, storage=None, steps=None, I0=None, want_diag=True, collisi
                 E=E, F=F, diag=diag)
     out = Ib if steps % 2 == 1 else Ia
     torch.cuda.synchronize()
-    if storage in (L.LBRT_BF16, L.LBRT_FP16):
+    if storage in (L.LBRT_BF16, L.LBRT_FP16, L.LBRT_BF16_SHIFTED, L.LBRT_FP16_SHIFTED):
         dec = torch.empty(prob.ndir * prob.ncell, dtype=torch.float32, device="cuda")
         L.lbrt_convert(ctx, out, storage, dec, L.LBRT_FP32)
         torch.cuda.synchronize()

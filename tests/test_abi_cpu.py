@@ -88,3 +88,19 @@ def test_validate_rejects_bad_descriptions():
     assert L.lbrt_validate(_desc(dirs=np.tile(dirs, (5, 1)), weights=np.tile(w, 5) / 5)) \
         == L.LBRT_E_INVAL
     assert "ndir" in L.lbrt_last_error()
+
+
+def test_state_bytes():
+    """lbrt_state_bytes / lbrt_state_e_offset: ndir ncell elements of the
+    storage type; the equilibrium-shifted forms add an FP32 E array at the
+    first multiple of 256 bytes after the 16-bit deviations."""
+    L = _lib()
+    assert L.state_bytes(L.LBRT_FP32, 110, 1000) == 4 * 110 * 1000
+    assert L.state_bytes(L.LBRT_FP64, 3, 7) == 8 * 21
+    assert L.state_bytes(L.LBRT_BF16, 50, 33) == 2 * 50 * 33
+    for st in (L.LBRT_BF16_SHIFTED, L.LBRT_FP16_SHIFTED):
+        off = L.state_e_offset(st, 50, 33)
+        assert off == 3328 and off % 256 == 0 and off >= 2 * 50 * 33
+        assert L.state_bytes(st, 50, 33) == off + 4 * 33
+    assert L.state_e_offset(L.LBRT_FP32, 50, 33) == 0
+    assert L.library().lbrt_state_bytes(9, 50, 33) == -1
