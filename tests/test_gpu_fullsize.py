@@ -227,3 +227,67 @@ def test_moving_192_adjoint_matches_finite_difference():
           flush=True)
     assert abs(fd - ad) < 1e-2 * abs(ad)
     ctx.close()
+
+
+def test_moving_192_fp64_adjoint_per_cell_finite_differences():
+    """The moving-fluid workload at its full size (192^3 x 146, 64 steps,
+    checkpoints every 8) in FP64 storage: d L / d kappa_a (eta = kappa_a, B = 1)
+    from the adjoint at 20 random cells inside the detector's light cone
+    (where the gradient is not 0), against central differences of two
+    forward runs per cell, (L(k + h) - L(k - h)) / (k_+ - k_-), h = 1e-3 k
+    (the perturbed values rounded to the float32 inputs).  Bound:
+    2e-6 |g| for the O(h^2) truncation, plus the rounding of the difference
+    of two FP64 values of L (about 5e5, each a fixed-order sum of ~10^7 FP64
+    terms): 8e-15 |L| / (k_+ - k_-), a few units in the last place of L.
+    The FP32 adjoint's gradient against the FP64 one: 1e-3 relative L2."""
+    torch = gh.torch_mod()
+    L = gh.lib()
+    from paper_2007_05718_amd import autodiff
+    prob = wl.moving(n=192, steps=64, alloc_state=False)
+    print(prob.name, prob.shape, prob.ndir, "FP64 adjoint + per-cell FD", flush=True)
+    ka, ks, _, vel, _ = gh.upload_fields(prob)
+    grads = {}
+    for st in (L.LBRT_FP64, L.LBRT_FP32):
+        ctx = L.lbrt_init(L.Desc.from_problem(prob, storage=st))
+        dt = torch.float64 if st == L.LBRT_FP64 else torch.float32
+        I0 = torch.zeros(prob.ndir * prob.ncell, dtype=dt, device="cuda")
+        Lv, ga, gs, ge = autodiff.detected_energy_gradient(ctx, I0, ka, ks, ka * 1.0, prob.steps,
+                                                           face=1, checkpoint_every=8, vel=vel)
+        grads[st] = (float(Lv), (ga + ge).double())
+        del I0
+        if st == L.LBRT_FP64:
+            ctx64 = ctx
+        else:
+            ctx.close()
+        torch.cuda.empty_cache()
+    L64, g64 = grads[L.LBRT_FP64]
+    e32 = float((grads[L.LBRT_FP32][1] - g64).norm() / g64.norm())
+    print(f"L fp64 {L64:.12e} fp32 {grads[L.LBRT_FP32][0]:.12e}; fp32 grad rel L2 {e32:.2e}",
+          flush=True)
+    assert e32 < 1e-3
+    gmax = float(g64.abs().max())
+    live = torch.nonzero(g64.abs() > 1e-3 * gmax).flatten().cpu().numpy()
+    rng = np.random.default_rng(2020)
+    cells = rng.choice(live, 20, replace=False)
+    I0 = torch.zeros(prob.ndir * prob.ncell, dtype=torch.float64, device="cuda")
+    worst = 0.0
+    with torch.no_grad():
+        for c in cells:
+            k0 = float(ka[c])
+            kp, km = np.float32(k0 * (1 + 1e-3)), np.float32(k0 * (1 - 1e-3))
+            Ls = []
+            for kv in (kp, km):
+                kk = ka.clone()
+                kk[c] = float(kv)
+                Ls.append(float(autodiff.detected_energy(ctx64, I0, kk, ks, kk * 1.0, prob.steps,
+                                                         face=1, checkpoint_every=prob.steps,
+                                                         vel=vel)))
+            dk = float(kp) - float(km)
+            fd = (Ls[0] - Ls[1]) / dk
+            ad = float(g64[c])
+            bound = 2e-6 * abs(ad) + 8e-15 * abs(L64) / dk
+            worst = max(worst, abs(fd - ad) / bound)
+            print(f"cell {c}: adjoint {ad:.10e} fd {fd:.10e} rel {abs(fd - ad) / abs(ad):.2e} "
+                  f"err/bound {abs(fd - ad) / bound:.2f}", flush=True)
+    ctx64.close()
+    assert worst < 1.0
