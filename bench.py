@@ -279,7 +279,7 @@ def time_coupling(L, torch, prob, reps: int = 10) -> dict:
             "frac_of_peak": round(bpc * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
-def time_batched(L, torch, ndomains=512, seed=4, sequential=True):
+def time_batched(L, torch, ndomains=512, seed=4, sequential=True, tune=True):
     """The batched opacity sweep: one lbrt_step_batched call against the same
     domains advanced one by one with lbrt_step (unless sequential=False).
     Returns a dict."""
@@ -339,6 +339,24 @@ def time_batched(L, torch, ndomains=512, seed=4, sequential=True):
                     "sequential_seconds": round(t_seq, 3),
                     "speedup_vs_sequential": round(t_seq / t_batch, 3)})
     b.close()
+    if tune:
+        # the tiling of each edge class tuned on batched launches of that
+        # class alone, then the same sweep again
+        from paper_2007_05718_amd import autotune
+        reps = autotune.tune_batch(doms)
+        b = L.lbrt_batch_create(doms)
+        L.lbrt_step_batched(b)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        L.lbrt_step_batched(b)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_tuned = e0.elapsed_time(e1) * 1e-3
+        out.update({"tuned_GDUPS": round(updates / t_tuned / 1e9, 2),
+                    "tuned_seconds": round(t_tuned, 3),
+                    "tuned_tilings": {r.key.split("|")[0]: "%dx%d z%d/%d" % r.best.as_tuple()
+                                      for r in reps}})
+        b.close()
     for dm in doms:
         dm["ctx"].close()
     return out

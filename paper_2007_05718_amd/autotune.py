@@ -12,8 +12,20 @@ only, so the state in ``I_a`` survives tuning.  ``TuningCache`` remembers the
 choice per problem key in a JSON file, so a serving process tunes once.
 
 The batched form (``lbrt_batch_create``) plans each domain with its context's
-tiling at creation time, so tuning a representative context before creating
-the batch carries over.
+tiling at creation time.  ``tune_batch`` groups a batch's domains by problem
+key (grid, directions, storage, fluid, boundaries) and times the candidate
+tilings of each group on a batched launch of that group alone, since a small
+domain runs very differently alone (a few blocks) and among hundreds of
+others; the fastest tiling is set on every context of the group before the
+caller creates the batch.
+
+There is no direction-blocking dimension: a block owns all the directions of
+its cells, because the collision needs every direction's streamed value of
+a cell at once (the moments E*, F* over all directions).  Splitting the
+directions over blocks would need a cross-block reduction of the moments per
+cell and plane, or a second pass over the state, each a per-step cost where
+the current split (the directions over the waves of one block, combined
+through LDS) has none.
 """
 from __future__ import annotations
 
@@ -22,7 +34,8 @@ import os
 from dataclasses import asdict, dataclass, field
 from typing import Iterable, List, Optional, Sequence, Tuple
 
-from . import (Context, lbrt_get_tiling, lbrt_set_tiling, lbrt_step)
+from . import (Context, lbrt_batch_create, lbrt_get_tiling, lbrt_set_tiling, lbrt_step,
+               lbrt_step_batched)
 
 TILES: Tuple[Tuple[int, int], ...] = ((64, 1), (32, 2), (16, 4), (8, 8))
 ZLENS: Tuple[int, ...] = (8, 16, 24, 32, 48, 64, 128)
@@ -177,3 +190,61 @@ class TuningCache:
         rep = tune_step(ctx, *args, **kw)
         self.put(key, rep)
         return rep.best
+
+
+@dataclass
+class BatchTuneReport:
+    key: str
+    domains: int
+    best: Tiling
+    best_ms: float
+    default: Tiling
+    default_ms: float
+    timings: List[Tuple[Tiling, float]] = field(default_factory=list)
+
+
+def tune_batch(domains: Sequence[dict], steps: int = 2, device_name: str = "",
+               max_candidates: int = 10, reps: int = 2) -> List[BatchTuneReport]:
+    """Tunes the tiling of a batch's domains per problem-key group and sets
+    the fastest on every context of the group (before the caller's
+    ``lbrt_batch_create``).  ``domains`` are the dicts ``lbrt_batch_create``
+    takes.  Each candidate is timed as one batched launch of the group alone
+    with every domain running ``steps`` steps (best of ``reps``); the timing
+    runs advance the domains' states, so tune before setting the initial
+    states, or on copies."""
+    import torch
+
+    groups: dict = {}
+    for dm in domains:
+        groups.setdefault(problem_key(dm["ctx"], device_name), []).append(dm)
+    reports: List[BatchTuneReport] = []
+    for key, ds in groups.items():
+        d = ds[0]["ctx"].desc.c
+        default = Tiling(*lbrt_get_tiling(ds[0]["ctx"]))
+        cands = candidate_tilings(d.nx, d.ny, d.nz, default, max_candidates=max_candidates)
+        sub = [dict(dm, nsteps=steps) for dm in ds]
+        timings: List[Tuple[Tiling, float]] = []
+        for t in cands:
+            for dm in ds:
+                lbrt_set_tiling(dm["ctx"], *t.as_tuple())
+            b = lbrt_batch_create(sub)
+            s = torch.cuda.current_stream()
+            lbrt_step_batched(b, stream=s.cuda_stream)   # warm-up
+            best = float("inf")
+            for _ in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(s)
+                lbrt_step_batched(b, stream=s.cuda_stream)
+                e1.record(s)
+                s.synchronize()
+                best = min(best, e0.elapsed_time(e1))
+            b.close()
+            timings.append((t, best))
+        bt, bms = min(timings, key=lambda x: x[1])
+        dms = next(ms for t, ms in timings if t == default)
+        for dm in ds:
+            lbrt_set_tiling(dm["ctx"], *bt.as_tuple())
+        reports.append(BatchTuneReport(key=key, domains=len(ds), best=bt, best_ms=bms,
+                                       default=default, default_ms=dms, timings=timings))
+    return reports
