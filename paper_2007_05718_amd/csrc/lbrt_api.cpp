@@ -542,9 +542,7 @@ int build_inflow(const lbrt_ctx *c, const lbrt_inflow *inflow, int32_t ninflow,
   return LBRT_OK;
 }
 
-int total_partials(const KParams &p) {
-  return p.nblocks + p.ngeneral + zface_blocks(p) + xface_blocks(p);
-}
+int total_partials(const KParams &p) { return p.nblocks + p.ngeneral + zface_blocks(p); }
 
 // What a step call needs after its arguments are checked: the kernel
 // parameters (tile plan for the call's ghost planes) and the compact ghost
@@ -623,10 +621,6 @@ int run_steps(lbrt_ctx *c, const StepCall &call, void *I_a, void *I_b, const flo
       e = launch_zface(d.storage, src, c->tab_dev, p, table,
                        partials + (size_t)(p.nblocks + p.ngeneral) * kStepPartials, s);
       if (e != hipSuccess) return hip_fail(e, "lbrt_step: launching the z-face flux kernel");
-      e = launch_xface(d.storage, src, c->tab_dev, p,
-                       partials + (size_t)(p.nblocks + p.ngeneral + zface_blocks(p)) *
-                                      kStepPartials, s);
-      if (e != hipSuccess) return hip_fail(e, "lbrt_step: launching the x-face flux kernel");
     }
     if (last && (E || F)) pk.flags |= KF_WRITE_EF;
     e = call.launch(src, dst, kappa_a, kappa_s, eta, vel, c->tab_dev, pk, table,

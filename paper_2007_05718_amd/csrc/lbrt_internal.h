@@ -293,10 +293,6 @@ hipError_t launch_adjoint(int storage, const void *I, const void *lam_next, void
 // Blocks of the z-face flux kernel (0 on a periodic z axis), and its launch:
 // per-block partials in the step kernel's format.
 int zface_blocks(const KParams &p);
-// x-face outflux of the pair kernel's face cells (16-bit storage, non-periodic x)
-int xface_blocks(const KParams &p);
-hipError_t launch_xface(int storage, const void *I, const void *tab, const KParams &p,
-                        double *partials, hipStream_t s);
 hipError_t launch_zface(int storage, const void *I, const void *tab, const KParams &p,
                         const InflowArgs *inflow, double *partials, hipStream_t s);
 

@@ -310,37 +310,6 @@ hipError_t launch_zface(int storage, const void *I, const void *tab, const KPara
   return hipGetLastError();
 }
 
-int xface_blocks(const KParams &p) {
-  if (!p.pair || p.periodic[0] || p.main_nzr <= 0) return 0;
-  const int za = p.main_zr0 * p.zlen;
-  const int zend = (p.main_zr0 + p.main_nzr) * p.zlen;
-  const int zb = zend < p.nz ? zend : p.nz;
-  const int64_t n = 2 * (int64_t)(p.ny - 2) * (zb > za ? zb - za : 0);
-  return (int)((n + kBlock - 1) / kBlock) * kZfaceGroups;
-}
-
-hipError_t launch_xface(int storage, const void *I, const void *tab, const KParams &p,
-                        double *partials, hipStream_t s) {
-  const int nb = xface_blocks(p) / kZfaceGroups;
-  if (nb == 0) return hipSuccess;
-  const dim3 grid(nb, kZfaceGroups);
-  switch (storage) {
-    case LBRT_BF16:
-      hipLaunchKernelGGL(xface_kernel<bf16_t>, grid, dim3(kBlock), 0, s,
-                         static_cast<const bf16_t *>(I), static_cast<const DirTab<float> *>(tab),
-                         p, partials);
-      break;
-    case LBRT_FP16:
-      hipLaunchKernelGGL(xface_kernel<f16_t>, grid, dim3(kBlock), 0, s,
-                         static_cast<const f16_t *>(I), static_cast<const DirTab<float> *>(tab),
-                         p, partials);
-      break;
-    default:   // the pair kernel runs for 16-bit storage only
-      return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
 hipError_t launch_inflow_table(const InflowCompact &c, InflowArgs *out, hipStream_t s) {
   hipLaunchKernelGGL(inflow_table_kernel, dim3(1), dim3(kBlock), 0, s, c, out);
   return hipGetLastError();

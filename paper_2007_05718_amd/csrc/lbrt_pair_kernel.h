@@ -28,7 +28,8 @@
 // (x_ghost_correction, as on the other paths).  The zeroing is two selects
 // per slot on every tile (a second copy of the slot loop for the face tiles
 // only would run the kernel out of scalar registers).  The x-face outflux of
-// the face cells is booked by xface_kernel.  With periodic x the tiles compute
+// the face cells is booked after each plane from their own values parked in
+// LDS, one slot per lane.  With periodic x the tiles compute
 // x in [2, nx - 2) and the columns x < 2, x >= nx - 2 are tiles of the
 // general (checked) path, like the face rows.  nx is even, so every pair
 // starts at an even cell index and its loads and stores are aligned.
@@ -236,10 +237,43 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
 
   // Face lanes: the neighbouring pair of a slot whose x-shifted taps lie
   // outside the box is a vacuum ghost (zeroed: its in-box load is
-  // discarded).  The x-face outflux of these cells is booked by
-  // xface_kernel (booking it here would keep more of each slot's record in
-  // scalar registers than the loop has).
+  // discarded).
   double fin = 0.0;
+  // x-face outflux of the face cells (diagnostics).  Every lane parks its
+  // own pair of each slot in LDS as the slot is streamed (one ds_write per
+  // slot; booking inside the slot loop would keep more of each slot's record
+  // in scalar registers than the loop has).  After the plane, lane l < M of
+  // a tile holding the -x face books slot l of the face pair (lane 0), and
+  // lane 32 + l of a tile holding the +x face books slot l of the pair
+  // (nx - 2, nx - 1): one LDS read and one FMA per lane and plane, with the
+  // slot's factor dt |n^x| / dx times the storage scale (0 unless the slot
+  // leaves through that face) fixed once per block.
+  __shared__ R ownx[NW][M][64];
+  // per booking lane: the factor (0 on a lane that books nothing), and the
+  // parked value's index in ownx times 2 plus the slot's dzn bit
+  T bf = T(0), fxb = T(0);
+  uint32_t bix = 0u;
+  {
+    const bool has_lo = diag && !perx && x0 == 0;
+    const bool has_hi = diag && !perx && x0 + NC >= nx;
+    const bool hi = lane >= 32;
+    const int slot = lane & 31;
+    if (slot < M && (hi ? has_hi : has_lo)) {
+      const DirTab<T> &d = dtab[q * M + slot];
+      bf = (hi ? d.s[0] > 0 : d.s[0] < 0) ? d.dxs : T(0);
+      const int src = hi ? (nx - 2 - x0) >> 1 : 0;
+      bix = (uint32_t)(((q * M + slot) * 64 + src) * 2 + d.dzn);
+    }
+  }
+  // (a slot that books nothing is skipped, not multiplied by 0: its parked
+  // value may be unwritten LDS, e.g. a slot the prologue did not load)
+  auto book_face = [&](bool prologue, int lastz) {
+    const int dzn = (int)(bix & 1u);
+    if (bf != T(0) && (prologue ? dzn != 0 : (dzn & lastz) == 0)) {
+      const R own = (&ownx[0][0][0])[bix >> 1];
+      fxb = fma(bf, lane >= 32 ? IO::hi(own) : IO::lo(own), fxb);
+    }
+  };
   auto zap = [&](const PairTab &d, R (&v)[4]) {
     const bool z0 = (d.flags & kPairSxPos) ? lox : hix;
     v[1] = z0 ? R(0) : v[1];
@@ -252,13 +286,15 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
     auto pro = [&]<int J>() {
       const PairTab &d = tb[J];
       carry[J][0] = carry[J][1] = T(0);
-      // (sz == 0: the carried plane has weight 0)
-      if (d.wz_old != T(0)) {
+      // (sz == 0: the carried plane has weight 0; for sz < 0 it is this
+      // block's first plane, whose own values the face cells book)
+      if (d.wz_old != T(0) || (d.flags & kPairDzn)) {
         int zl = (d.flags & kPairDzn) ? zb : zb - 1;
         if (perz) zl = wrap(zl, nz);
         R v[4];
         const bool in = (unsigned)zl < (unsigned)nz;
         load4(d, in_bytes + (int64_t)min(max(zl, 0), nz - 1) * pc * SZ, v);
+        ownx[q][J][lane] = v[0];
         zap(d, v);
         T a, b;
         interp2(d, v, a, b);
@@ -268,6 +304,7 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
     };
     unroll<0, M>(pro);
   }
+  book_face(true, 0);
 
   // the slots of this wave with an inflow ghost plane on an x face that this
   // tile touches (bit J for slot J)
@@ -326,6 +363,7 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
         const PairTab &d = tb[J];
         if constexpr (J + D < M)
           load4(tb[J + D], (tb[J + D].flags & kPairDzn) ? p1 : p0, pf[J + D]);
+        ownx[q][J][lane] = pf[J][0];
         zap(d, pf[J]);
         T Pn[2];
         interp2(d, pf[J], Pn[0], Pn[1]);
@@ -447,6 +485,9 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
         }
       }
     }
+    // this plane's x-face outflux (own values parked during the slot loop;
+    // booked here, where the plane's streamed values are no longer live)
+    book_face(false, z + 1 >= ze ? 1 : 0);
   }
 
   if (diag) {
@@ -455,6 +496,8 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
     for (int k = 0; k < kStepPartials; ++k) v[k] = 0.0;
     v[0] = sE;
     v[1] = sEs;
+    v[2] = lane < 32 ? (double)fxb : 0.0;
+    v[3] = lane >= 32 ? (double)fxb : 0.0;
     v[8] = fin;
     block_sums<kStepPartials, NW>(v, partials + (int64_t)blockIdx.x * kStepPartials);
   }

@@ -1312,50 +1312,6 @@ zface_kernel(const S *__restrict__ I, const DirTab<typename StoreTraits<S>::T> *
       v, partials + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * kStepPartials);
 }
 
-// ---------------------------------------------------------------------------
-// Outflux through the x faces of the face cells that the pair kernel
-// computes (non-periodic x: columns 0 and nx - 1 of rows [1, ny - 1) in its
-// z ranges), as per-block partials in the step kernel's format (columns 2
-// and 3: -x and +x).  One thread per face cell.  The x face has the first
-// claim on a population that leaves along several axes (book_outflux), so a
-// face cell books dt |n^x| / dx of each population leaving through it.
-// ---------------------------------------------------------------------------
-template <typename S>
-__global__ void __launch_bounds__(kBlock)
-xface_kernel(const S *__restrict__ I, const DirTab<typename StoreTraits<S>::T> *__restrict__ tab,
-             const KParams p, double *__restrict__ partials) {
-  using Tr = StoreTraits<S>;
-  using T = typename Tr::T;
-  const int nx = p.nx, rows = p.ny - 2;
-  const int64_t pc = (int64_t)nx * p.ny;
-  const int za = p.main_zr0 * p.zlen;
-  const int zb = min(p.nz, (p.main_zr0 + p.main_nzr) * p.zlen);
-  const int64_t nrow = (int64_t)rows * (zb - za);
-  const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;   // over 2 nrow
-  const int g = blockIdx.y;   // direction group: slots g, g + G, ...
-  double v[kStepPartials];
-#pragma unroll
-  for (int j = 0; j < kStepPartials; ++j) v[j] = 0.0;
-  if (k < 2 * nrow) {
-    const int face = k >= nrow;   // 0: x = 0, 1: x = nx - 1
-    const int64_t r = face ? k - nrow : k;
-    const int z = za + (int)(r / rows), y = 1 + (int)(r % rows);
-    const int64_t cell = (int64_t)z * pc + (int64_t)y * nx + (face ? nx - 1 : 0);
-    T out = T(0);
-    for (int i = g; i < p.ndir; i += (int)gridDim.y) {
-      const DirTab<T> &d = tab[i];
-      if (d.s[0] != 0 && (d.s[0] > 0) == (face == 1)) {
-        T own = Tr::ld(I + (d.plane_off / (int64_t)sizeof(S)) + cell);
-        if (Tr::kReduced) own *= d.scale;
-        out += d.delta[0] * own;
-      }
-    }
-    v[2 + face] = (double)out;
-  }
-  block_sums<kStepPartials>(
-      v, partials + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * kStepPartials);
-}
-
 }  // namespace lbrt
 
 #include "lbrt_pair_kernel.h"
