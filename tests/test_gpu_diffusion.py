@@ -88,3 +88,16 @@ def test_diffusion_128_full_run_follows_moment_recursion():
         if done <= 500:
             assert abs(got[2] / want[2] - 1) < 1e-5
     ctx.close()
+
+
+def test_diffusion_jittered_long_run_against_oracle():
+    """The diffusion configuration with its +-5 % per-cell kappa_s jitter
+    (which the moment recursion above does not cover), scaled to 32^3 with
+    a sigma = 4 pulse, over 200 steps of the periodic box: FP32 against the
+    FP64 oracle element by element (check of test_gpu_parity: 1e-5)."""
+    from test_gpu_parity import check, oracle_run
+    p = wl.diffusion(n=32, sigma=4.0, steps=200, jitter=0.05)
+    print(p.name, p.shape, p.ndir, p.steps, "steps, jitter 0.05", flush=True)
+    res = gh.run_problem(p, storage=gh.lib().LBRT_FP32, want_diag=False)
+    I, E, F, _ = oracle_run(p, res["I0_eff"], p.steps)
+    check(res, I, E, F, 1e-5)
