@@ -180,6 +180,10 @@ struct KParams {
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;   // waves per block = direction quarters
 constexpr int kTileCells = 64;        // cells per xy tile (one per lane)
+// E cells a block of equilibrium-shifted storage stages per plane: the
+// tile and its one-cell halo, (64 / tx + 2)(tx + 2) <= 198, one per lane of
+// four waves
+constexpr int kStagePos = 256;
 constexpr int kDiag = LBRT_DIAG_LEN;
 // Per-block diagnostic partials of the step kernel: sum E, sum E*, outflux
 // through the faces -x, +x, -y, +y, -z, +z, influx from inflow ghosts.

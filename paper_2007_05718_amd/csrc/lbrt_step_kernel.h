@@ -785,14 +785,14 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
 
   // Prologue: the carried plane of every slot (P at zb - 1 for sz > 0, at zb
   // for sz < 0; nothing for sz == 0).  On the main path a plane outside the
-  // box is vacuum (its clamped loads are weighted by 0).
+  // box is vacuum (its clamped loads are weighted by 0).  Shifted storage
+  // carries the plane value of the population itself, s_i P + w_i P_E (P_E:
+  // E pulled along the slot), one register per slot.
   T carry[M];
-  T carryE[M];   // shifted storage: the carried plane of E pulled along the slot
   {
     auto pro = [&]<int J>() {
       const DirTab<T> &d = tb[J];
       carry[J] = T(0);
-      carryE[J] = T(0);
       if (d.s[2] != 0) {
         int zl = d.s[2] > 0 ? zb - 1 : zb;
         if (perz) zl = wrap(zl, nz);
@@ -808,13 +808,14 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
           if constexpr (SH) {
             T e[4];
             load4E(d, ein_bytes + (int64_t)zc * pc * 4, e);
-            carryE[J] = (in ? T(1) : T(0)) * interp4(d, e[0], e[1] * k1, e[2], e[3] * k1);
+            const T PE = (in ? T(1) : T(0)) * interp4(d, e[0], e[1] * k1, e[2], e[3] * k1);
+            carry[J] = fma(d.w, PE, carry[J] * d.scale);
             if (diag && d.s[2] < 0) fx = fma(ko * (d.delta[0] * d.w), e[0], fx);
           }
         } else {
           T PE;
           carry[J] = general_P(d, q * M + J, zl, d.s[2] < 0, PE);
-          carryE[J] = PE;
+          if constexpr (SH) carry[J] = fma(d.w, PE, carry[J] * d.scale);
         }
       }
     };
@@ -835,17 +836,71 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
   // before the collision's stores.
   constexpr int D = pf_depth<S, MOVING>(M);
   T pf[M][4];
-  T pfE[M][4];   // shifted storage: the slots' E taps, in flight with pf
   auto issue_first = [&](int zn) {
     const char *const p0 = in_bytes + (int64_t)zn * pc * SZ;
     const char *const p1 = in_bytes + plane_above(zn) * SZ;
-    const char *const e0 = ein_bytes + (int64_t)zn * pc * 4;
-    const char *const e1 = ein_bytes + plane_above(zn) * 4;
-    auto one = [&]<int J>() {
-      load4(tb[J], tb[J].dzn_a ? p1 : p0, pf[J]);
-      if constexpr (SH) load4E(tb[J], tb[J].dzn_a ? e1 : e0, pfE[J]);
-    };
+    auto one = [&]<int J>() { load4(tb[J], tb[J].dzn_a ? p1 : p0, pf[J]); };
     unroll<0, D>(one);
+  };
+
+  // Shifted storage, main path: every slot of a plane interpolates E at the
+  // same few cells (the tile's rows y0 - 1 .. y0 + ty and columns x0 - 1 ..
+  // x0 + tx of the plane and of the plane above), so the block stages those
+  // rows of the E array in LDS once per plane, and a slot's four E taps are
+  // LDS reads instead of four global loads.  Staged plane j of the range is
+  // sp(j) = zb for j = 0, else the plane above zb + j - 1; plane z = zb + k
+  // reads sp(k) and sp(k + 1) (ring buffers k % 3 and (k + 1) % 3).  sp(k + 3)
+  // is loaded during plane k (with the next plane's first taps) and written
+  // at the end of plane k + 1's slot loop, between the barriers that follow
+  // the last reads of its buffer and precede its first.  Staged column c
+  // holds cell x0 - 1 + c wrapped (periodic x) or clamped into the box: the
+  // taps a face or ragged lane takes there are the ones the global path takes.
+  constexpr bool STAGE = SH && MAIN;
+  static_assert(!STAGE || NW * 64 >= kStagePos, "four waves stage the E rows");
+  __shared__ float estage[STAGE ? 3 : 1][STAGE ? kStagePos : 1];
+  const int srow = tx + 2;                               // staged cells per row
+  const int eown = ((lane >> txlog) + 1) * srow + (lane & (tx - 1)) + 1;
+  uint32_t soff = 0u;       // byte offset in an E plane of this lane's staged cell
+  bool sok = false;         // the lane stages a cell (waves 0 .. 3)
+  float spend = 0.0f;       // staged value in flight (loaded a plane ahead)
+  int sb = 0;               // ring buffer of sp(k) for the current plane k
+  auto stage_plane = [&](int j) -> int64_t {
+    return j == 0 ? (int64_t)zb * pc : plane_above(zb + j - 1);
+  };
+  auto stage_load = [&](int j) {
+    if (sok) spend = ldo<float>(reinterpret_cast<const float *>(ein_bytes) + stage_plane(j), soff);
+  };
+  auto stage_write = [&](int b) {
+    if (sok) estage[b][q * 64 + lane] = spend;
+  };
+  if constexpr (STAGE) {
+    const int pidx = q * 64 + lane;
+    sok = pidx < (kTileCells / tx + 2) * srow;
+    if (sok) {
+      const int r = pidx / srow;
+      int gx = x0 - 1 + (pidx - r * srow);
+      gx = perx ? ((gx % nx) + nx) % nx : min(max(gx, 0), nx - 1);
+      soff = (uint32_t)(gx + nx * (y0 - 1 + r)) * 4u;
+    }
+    if (zb < ze) {
+      stage_load(0);
+      stage_write(0);
+      stage_load(1);
+      stage_write(1);
+      if (zb + 1 < ze) stage_load(2);
+      __syncthreads();
+    }
+  }
+  // the four E taps of slot d from ring buffer b0 (its new plane is z) or
+  // b1 (the plane above): rows y and y - sy, unshifted and x-shifted
+  auto lds4E = [&](const DirTab<T> &d, int b0, int b1, T (&v)[4]) {
+    const float *e = &estage[d.dzn_a ? b1 : b0][0];
+    const int xs = (int)(d.mxm & 1u) - (int)(d.mxp & 1u);
+    const int ys = d.row_shift > 0 ? srow : (d.row_shift < 0 ? -srow : 0);
+    v[0] = (T)e[eown];
+    v[1] = (T)e[eown + xs];
+    v[2] = (T)e[eown + ys];
+    v[3] = (T)e[eown + ys + xs];
   };
   if constexpr (MAIN)
     if (zb < ze) issue_first(zb);
@@ -897,8 +952,9 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
       // plane above a non-periodic box is clamped into it and weighted 0
       const char *const p0 = in_bytes + cz * SZ;
       const char *const p1 = in_bytes + plane_above(z) * SZ;
-      const char *const e0 = ein_bytes + cz * 4;
-      const char *const e1 = ein_bytes + plane_above(z) * 4;
+      // shifted storage: ring buffers of this plane and of the plane above
+      const int sb1 = sb == 2 ? 0 : sb + 1;
+      T pfE[M][4];   // a slot's E taps, read from LDS one slot ahead
       // the plane above a non-periodic box is vacuum: weight 0
       const int gh = (!perz && z + 1 >= nz) ? 1 : 0;
       // the plane above the last plane of the range belongs to the next block
@@ -911,9 +967,10 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
       // J + D before interpolating its own.
       auto slot = [&]<int J, bool FACE>() {
         const DirTab<T> &d = tb[J];
-        if constexpr (J + D < M) {
-          load4(tb[J + D], tb[J + D].dzn_a ? p1 : p0, pf[J + D]);
-          if constexpr (SH) load4E(tb[J + D], tb[J + D].dzn_a ? e1 : e0, pfE[J + D]);
+        if constexpr (J + D < M) load4(tb[J + D], tb[J + D].dzn_a ? p1 : p0, pf[J + D]);
+        if constexpr (SH) {
+          if constexpr (J == 0) lds4E(d, sb, sb1, pfE[0]);
+          if constexpr (J + 1 < M) lds4E(tb[J + 1], sb, sb1, pfE[J + 1]);
         }
         const T(&cur)[4] = pf[J];
         T c1 = cur[1], c3 = cur[3];
@@ -930,18 +987,20 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
         const T Pn = interp4(d, cur[0], c1, cur[2], c3);
         // the new plane above a non-periodic box is vacuum
         const T wn = zero_if(d.wz_new, d.dzn & gh);
-        T sv = fma(d.wz_old, carry[J], wn * Pn);
-        if (Tr::kReduced) sv *= d.scale;
         if constexpr (SH) {
           const T(&ce)[4] = pfE[J];
           const T PEn = interp4(d, ce[0], ce[1] * k1, ce[2], ce[3] * k1);
           if constexpr (FACE)
             fx = fma(ko * zero_if(d.delta[0] * d.w, d.dzn & lastz), ce[0], fx);
-          sv = fma(d.w, fma(d.wz_old, carryE[J], wn * PEn), sv);
-          carryE[J] = PEn;
+          const T Ph = fma(d.w, PEn, Pn * d.scale);
+          Is[J] = fma(d.wz_old, carry[J], wn * Ph);
+          carry[J] = Ph;
+        } else {
+          T sv = fma(d.wz_old, carry[J], wn * Pn);
+          if (Tr::kReduced) sv *= d.scale;
+          Is[J] = sv;
+          carry[J] = Pn;
         }
-        Is[J] = sv;
-        carry[J] = Pn;
         accumulate<MOVING, J, M>(m, tb, Is, vx, vy, vz, dtWk);
       };
       auto body_face = [&]<int J>() { slot.template operator()<J, true>(); };
@@ -950,19 +1009,27 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
         unroll<0, M>(body_face);
       else
         unroll<0, M>(body);
+      if constexpr (STAGE) {
+        // sp(k + 2), loaded during the previous plane, into the buffer that
+        // plane k - 1 read last (k = z - zb)
+        if (z + 1 < ze) stage_write(sb1 == 2 ? 0 : sb1 + 1);
+      }
     } else {
       auto body = [&]<int J>() {
         const DirTab<T> &d = tb[J];
         T PEn;
         const T Pn = general_P(d, q * M + J, new_plane(d, z), own_plane(d, z), PEn);
-        T sv = fma(d.wz_old, carry[J], d.wz_new * Pn);
-        if (Tr::kReduced) sv *= d.scale;
+        T sv;
         if constexpr (SH) {
-          sv = fma(d.w, fma(d.wz_old, carryE[J], d.wz_new * PEn), sv);
-          carryE[J] = PEn;
+          const T Ph = fma(d.w, PEn, Pn * d.scale);
+          sv = fma(d.wz_old, carry[J], d.wz_new * Ph);
+          carry[J] = Ph;
+        } else {
+          sv = fma(d.wz_old, carry[J], d.wz_new * Pn);
+          if (Tr::kReduced) sv *= d.scale;
+          carry[J] = Pn;
         }
         Is[J] = valid ? sv : T(0);
-        carry[J] = Pn;
         accumulate<MOVING, J, M>(m, tb, Is, vx, vy, vz, dtWk);
       };
       unroll<0, M>(body);
@@ -1049,6 +1116,8 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
     auto issue_next = [&]() {
       if constexpr (MAIN)
         if (z + 1 < ze) issue_first(z + 1);
+      if constexpr (STAGE)
+        if (z + 2 < ze) stage_load(z - zb + 3);
     };
 
     // the new populations of plane z: a uniform base per slot plus the
@@ -1196,6 +1265,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
         sEs += (double)Es;
       }
     }
+    if constexpr (STAGE) sb = sb == 2 ? 0 : sb + 1;
   }
 
   if (diag) {
