@@ -12,10 +12,18 @@
 // sx = 0 its weight is 0), an aligned load like the own pair, by one
 // v_perm_b32 of the two dwords with the slot's byte selector.
 //
+// Equilibrium-shifted 16-bit storage takes it too: the block stages the E
+// cells its slots' taps read (three rows of 130 cells per plane) in LDS, a
+// slot pulls E with the populations' weights from there, carries the
+// population's plane value s_i P + w_i P_E, and stores the deviation from
+// w_i E' and E' itself (the same arithmetic as the other paths).
+//
 // Only the 16-bit forms take this path.  With FP32 storage a two-cell lane
 // holds twice the bytes per slot in flight, so under the same register
 // budget it keeps half as many slots ahead per cell and waits longer on its
-// loads than the one-cell main kernel; the main kernel serves FP32.
+// loads than the one-cell main kernel (built under the 128-VGPR cap of two
+// blocks per CU it spills even with two slots ahead); the main kernel
+// serves FP32.
 // The slot constants come from compact records (PairTab, PairColl), each
 // read with one wide scalar load per plane.
 //
@@ -120,18 +128,32 @@ template <> struct PairIO<f16_t> : PairIO16<f16_t> {
   }
 };
 
-// Compiled combinations: static fluid, BF16 / FP16 storage, the 56- and
-// 112-slot buckets.
+// Equilibrium-shifted storage: the stored deviations are BF16 / FP16 pairs
+// like the plain forms'.
+template <> struct PairIO<bf16s_t> : PairIO<bf16_t> {};
+template <> struct PairIO<f16s_t> : PairIO<f16_t> {};
+
+// Compiled combinations: static fluid, BF16 / FP16 storage (plain or
+// equilibrium-shifted), the 56- and 112-slot buckets.
 template <typename S, int NB, bool MOVING>
 constexpr bool pair_kernel_exists() {
-  return !MOVING && sizeof(S) == 2 && !StoreTraits<S>::kShifted && (NB == 56 || NB == 112);
+  return !MOVING && sizeof(S) == 2 && (NB == 56 || NB == 112);
 }
 
+// Equilibrium-shifted storage: a block stages the E cells that its slots'
+// taps read (rows y - 1 .. y + 1, columns x0 - 1 .. x0 + 128) in LDS per
+// plane; staged cell (r, c) sits at element 1 + r kPairSRow + c, so that a
+// lane's own pair (c = 2l + 1, 2l + 2) is one aligned 8-byte read.
+constexpr int kPairSRow = 130;
+constexpr int kPairSPos = 3 * kPairSRow;
+constexpr int kPairSBuf = kPairSPos + 2;
+
 // Slots whose four row loads (4 VGPRs) are in flight ahead of the slot being
-// interpolated.
+// interpolated: 4, and 2 for shifted storage, whose E taps and staging take
+// the registers of two (with 3 it needs 133 VGPRs: one block per CU).
 template <typename S>
 constexpr int pair_pf_depth(int m) {
-  return m < 4 ? m : 4;
+  return StoreTraits<S>::kShifted ? (m < 2 ? m : 2) : (m < 4 ? m : 4);
 }
 
 // Plane value from four taps with the slot's per-axis weights: the same
@@ -176,6 +198,12 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
   const T dt = (T)p.dt;
   const bool diag = (p.flags & KF_DIAG) != 0;
   const bool stoch = (p.flags & KF_STOCH) != 0;
+  // Equilibrium-shifted storage: the states' FP32 E arrays (byte offset e_off)
+  constexpr bool SH = StoreTraits<S>::kShifted;
+  const char *const ein_bytes = reinterpret_cast<const char *>(Iin) + (SH ? p.e_off : 0);
+  char *const eout_bytes = reinterpret_cast<char *>(Iout) + (SH ? p.e_off : 0);
+  // staged E cells, three plane buffers (see the staging below)
+  __shared__ __attribute__((aligned(16))) float estage[SH ? 3 : 1][SH ? kPairSBuf : 2];
 
   // stream lanes: cells (x, x + 1), stored when inside [pair_x0, pair_xend);
   // a lane beyond the row reads the last pair
@@ -253,6 +281,10 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
   // parked value's index in ownx times 2 plus the slot's dzn bit
   T bf = T(0), fxb = T(0);
   uint32_t bix = 0u;
+  // shifted storage: the E part of the booked value (dt |n^x| / dx times w,
+  // or 0) and the staged index of the face cell (row y)
+  T bfE = T(0);
+  int eix = 0;
   {
     const bool has_lo = diag && !perx && x0 == 0;
     const bool has_hi = diag && !perx && x0 + NC >= nx;
@@ -261,17 +293,22 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
     if (slot < M && (hi ? has_hi : has_lo)) {
       const DirTab<T> &d = dtab[q * M + slot];
       bf = (hi ? d.s[0] > 0 : d.s[0] < 0) ? d.dxs : T(0);
+      if constexpr (SH) bfE = bf != T(0) ? d.delta[0] * d.w : T(0);
+      eix = 1 + kPairSRow + (hi ? nx - x0 : 1);
       const int src = hi ? (nx - 2 - x0) >> 1 : 0;
       bix = (uint32_t)(((q * M + slot) * 64 + src) * 2 + d.dzn);
     }
   }
   // (a slot that books nothing is skipped, not multiplied by 0: its parked
   // value may be unwritten LDS, e.g. a slot the prologue did not load)
-  auto book_face = [&](bool prologue, int lastz) {
+  // (shifted storage: the staged E of the face cell at the booked plane is in
+  // ring buffer b0 (the plane) or b1 (the plane above, dzn slots))
+  auto book_face = [&](bool prologue, int lastz, int b0, int b1) {
     const int dzn = (int)(bix & 1u);
     if (bf != T(0) && (prologue ? dzn != 0 : (dzn & lastz) == 0)) {
       const R own = (&ownx[0][0][0])[bix >> 1];
       fxb = fma(bf, lane >= 32 ? IO::hi(own) : IO::lo(own), fxb);
+      if constexpr (SH) fxb = fma(bfE, estage[dzn ? b1 : b0][eix], fxb);
     }
   };
   auto zap = [&](const PairTab &d, R (&v)[4]) {
@@ -280,7 +317,82 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
     v[3] = z0 ? R(0) : v[3];
   };
 
-  // prologue: the carried plane value of every slot and both cells
+  // Shifted storage: every slot of a plane interpolates E at the tile's
+  // cells and their one-cell halo, of the plane and of the plane above, so
+  // the block stages those cells in LDS (kPairSRow) per plane: staged plane
+  // j of the range is sp(j) = zb for j = 0, else the plane above zb + j - 1,
+  // in ring buffer j % 3; plane zb + k reads buffers k % 3 and (k + 1) % 3.
+  // sp(k + 2) is loaded during plane k - 1 and written during plane k,
+  // between the barrier after its slot loop (every wave has then finished
+  // with the buffer: its last readers are plane k - 1's slot loop and face
+  // booking) and the barrier before its collision (plane k + 1 reads it
+  // first).  The prologue stages plane zb - 1 in buffer 2 for the carried
+  // planes.  Staged column c holds cell x0 - 1 + c wrapped (periodic x) or
+  // clamped into the box; a face cell's x-shifted E tap is zeroed like its
+  // population's.
+  constexpr int KS = SH ? (kPairSPos + 64 * NW - 1) / (64 * NW) : 1;
+  uint32_t soff[KS];
+  float spend[KS];
+  int sb = 0;   // ring buffer of the current plane
+  auto stage_ok = [&](int k) { return q * 64 + lane + k * 64 * NW < kPairSPos; };
+  if constexpr (SH) {
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      soff[k] = 0u;
+      spend[k] = 0.0f;
+      if (stage_ok(k)) {
+        const int pidx = q * 64 + lane + k * 64 * NW;
+        const int r = pidx / kPairSRow;
+        int gx = x0 - 1 + (pidx - r * kPairSRow);
+        gx = perx ? ((gx % nx) + nx) % nx : min(max(gx, 0), nx - 1);
+        soff[k] = (uint32_t)(gx + nx * (y - 1 + r)) * 4u;
+      }
+    }
+  }
+  auto stage_load = [&](int64_t plane_cells) {
+#pragma unroll
+    for (int k = 0; k < KS; ++k)
+      if (stage_ok(k))
+        spend[k] = ldo<float>(reinterpret_cast<const float *>(ein_bytes) + plane_cells, soff[k]);
+  };
+  auto stage_write = [&](int b) {
+#pragma unroll
+    for (int k = 0; k < KS; ++k)
+      if (stage_ok(k)) estage[b][1 + q * 64 + lane + k * 64 * NW] = spend[k];
+  };
+  auto stage_plane = [&](int j) -> int64_t {
+    return j == 0 ? (int64_t)zb * pc : plane_above(zb + j - 1);
+  };
+  // E of both cells of a slot at ring buffer b0 (its new plane is the
+  // current one) or b1 (the plane above), from the staged rows y and y - sy:
+  // own pair and the one neighbouring cell that the x-shifted taps need
+  const int eown = 2 + kPairSRow + 2 * lane;
+  auto plane_E = [&](const PairTab &d, int b0, int b1, T &PElo, T &PEhi) {
+    const float *eb = &estage[(d.flags & kPairDzn) ? b1 : b0][0];
+    const bool pos = (d.flags & kPairSxPos) != 0;
+    const int ys = d.row_off > 0 ? kPairSRow : (d.row_off < 0 ? -kPairSRow : 0);
+    const int nbo = pos ? -1 : 2;
+    const f32x2 a = *reinterpret_cast<const f32x2 *>(eb + eown);
+    const f32x2 b = *reinterpret_cast<const f32x2 *>(eb + eown + ys);
+    T an = eb[eown + nbo], bn = eb[eown + ys + nbo];
+    if (pos ? lox : hix) an = bn = T(0);
+    PElo = interp4w(d, a.x, pos ? an : a.y, b.x, pos ? bn : b.y);
+    PEhi = interp4w(d, a.y, pos ? a.x : an, b.y, pos ? b.x : bn);
+  };
+  if constexpr (SH) {
+    if (zb < ze) {
+      int zl = zb - 1;
+      if (perz) zl = wrap(zl, nz);
+      stage_load((int64_t)min(max(zl, 0), nz - 1) * pc);
+      stage_write(2);
+      stage_load(stage_plane(0));
+      stage_write(0);
+      __syncthreads();
+    }
+  }
+
+  // prologue: the carried plane value of every slot and both cells (shifted
+  // storage: of the population, s_i P + w_i P_E)
   T carry[M][2];
   {
     auto pro = [&]<int J>() {
@@ -300,11 +412,25 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
         interp2(d, v, a, b);
         carry[J][0] = (in ? T(1) : T(0)) * a;
         carry[J][1] = (in ? T(1) : T(0)) * b;
+        if constexpr (SH) {
+          T ea, eb;
+          plane_E(d, 2, 0, ea, eb);
+          carry[J][0] = fma(d.w, (in ? T(1) : T(0)) * ea, carry[J][0] * d.scale);
+          carry[J][1] = fma(d.w, (in ? T(1) : T(0)) * eb, carry[J][1] * d.scale);
+        }
       }
     };
     unroll<0, M>(pro);
   }
-  book_face(true, 0);
+  book_face(true, 0, 0, 0);
+  if constexpr (SH) {
+    if (zb < ze) {
+      stage_load(stage_plane(1));
+      stage_write(1);
+      if (zb + 1 < ze) stage_load(stage_plane(2));
+      __syncthreads();
+    }
+  }
 
   // the slots of this wave with an inflow ghost plane on an x face that this
   // tile touches (bit J for slot J)
@@ -320,7 +446,7 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
   }
 
   __shared__ T red[NW][4][NC];
-  __shared__ T coef[5][NC];
+  __shared__ T coef[SH ? 6 : 5][NC];   // c, alpha, beta (x3); E' (shifted storage)
   R pf[M][4];
   auto issue_first = [&](int zn) {
     const char *const p0 = in_bytes + (int64_t)zn * pc * SZ;
@@ -357,6 +483,7 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
     {
       const char *const p0 = in_bytes + cz * SZ;
       const char *const p1 = in_bytes + plane_above(z) * SZ;
+      const int sb1 = sb == 2 ? 0 : sb + 1;   // shifted storage: the plane above
       // plane above the box: vacuum (wave-uniform, so the zeroing is scalar)
       const int gh = __builtin_amdgcn_readfirstlane((!perz && z + 1 >= nz) ? 1 : 0);
       auto slot = [&]<int J>() {
@@ -365,15 +492,24 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
           load4(tb[J + D], (tb[J + D].flags & kPairDzn) ? p1 : p0, pf[J + D]);
         ownx[q][J][lane] = pf[J][0];
         zap(d, pf[J]);
-        T Pn[2];
+        T Pn[2], PE[2];
         interp2(d, pf[J], Pn[0], Pn[1]);
+        if constexpr (SH) plane_E(d, sb, sb1, PE[0], PE[1]);
         const T wn = zero_if(d.wz_new, (int)((d.flags >> 1) & 1u) & gh);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          T sv = fma(d.wz_old, carry[J][h], wn * Pn[h]);
-          if constexpr (sizeof(S) == 2) sv *= d.scale;
+          T sv;
+          if constexpr (SH) {
+            // the population's plane value s_i P + w_i P_E
+            const T Ph = fma(d.w, PE[h], Pn[h] * d.scale);
+            sv = fma(d.wz_old, carry[J][h], wn * Ph);
+            carry[J][h] = Ph;
+          } else {
+            sv = fma(d.wz_old, carry[J][h], wn * Pn[h]);
+            if constexpr (sizeof(S) == 2) sv *= d.scale;
+            carry[J][h] = Pn[h];
+          }
           Is[J][h] = sv;
-          carry[J][h] = Pn[h];
           // moments as residuals against the wave's first slot (see accumulate)
           Es[h] += sv;
           if constexpr (J == 0) ref[h] = sv * d.invw;
@@ -433,7 +569,11 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
         const CoefE<T> ce = coef_E<T>(p.mode, p.lambda_iters, dt, Sm, kat, kst, et);
         coef[0][cc] = ce.c;
         coef[1][cc] = ce.alpha;
+        if constexpr (SH) coef[5][cc] = ce.En;
         if (valid_c) {
+          // the new E, part of a shifted state
+          if constexpr (SH)
+            *reinterpret_cast<float *>(eout_bytes + (cz + ocell) * 4) = ce.En;
           if (p.flags & KF_WRITE_EF) Eout[cz + ocell] = ce.En;
           if (diag) {
             sE += (double)ce.En;
@@ -450,6 +590,11 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
     // the next plane's medium and first loads go out before the stores
     load_medium(cz_next, om);
     if (z + 1 < ze) issue_first(z + 1);
+    if constexpr (SH) {
+      // sp(k + 2) into the buffer that plane k - 1 read last; sp(k + 3) loaded
+      if (z + 1 < ze) stage_write(sb == 0 ? 2 : sb - 1);
+      if (z + 2 < ze) stage_load(stage_plane(z - zb + 3));
+    }
     __syncthreads();
 
     // ---- collide and store both cells of every slot
@@ -461,6 +606,8 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
       b1 = *reinterpret_cast<const f32x2 *>(&coef[3][2 * lane]);
       b2 = *reinterpret_cast<const f32x2 *>(&coef[4][2 * lane]);
     }
+    f32x2 en2 = {T(0), T(0)};   // shifted storage: both cells' new E
+    if constexpr (SH) en2 = *reinterpret_cast<const f32x2 *>(&coef[5][2 * lane]);
     char *const outz = reinterpret_cast<char *>(Iout) + cz * SZ;
     const uint32_t ost = opaque_lane(o0);
     const PairColl *__restrict__ tbc = ctab + opaque(q * M);
@@ -477,6 +624,11 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
         if (d.inv_scale != T(0)) {   // a direction (padding slots carry 0)
           T o0v = collide_pair(d, c2.x, a2.x, b0.x, b1.x, b2.x, Is[jj][0], lamzero);
           T o1v = collide_pair(d, c2.y, a2.y, b0.y, b1.y, b2.y, Is[jj][1], lamzero);
+          if constexpr (SH) {
+            // stored: the deviation from w_i E'
+            o0v = fma(-d.w, en2.x, o0v);
+            o1v = fma(-d.w, en2.y, o1v);
+          }
           if constexpr (sizeof(S) == 2) {
             o0v *= d.inv_scale;
             o1v *= d.inv_scale;
@@ -487,7 +639,8 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
     }
     // this plane's x-face outflux (own values parked during the slot loop;
     // booked here, where the plane's streamed values are no longer live)
-    book_face(false, z + 1 >= ze ? 1 : 0);
+    book_face(false, z + 1 >= ze ? 1 : 0, sb, sb == 2 ? 0 : sb + 1);
+    sb = sb == 2 ? 0 : sb + 1;
   }
 
   if (diag) {

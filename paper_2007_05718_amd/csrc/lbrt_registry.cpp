@@ -95,7 +95,9 @@ StepLauncher step_launcher(int storage, int bucket_index, bool moving) {
 }
 
 bool pair_available(int storage, int nb, bool moving) {
-  return !moving && (storage == LBRT_BF16 || storage == LBRT_FP16) &&
+  return !moving &&
+         (storage == LBRT_BF16 || storage == LBRT_FP16 || storage == LBRT_BF16_SHIFTED ||
+          storage == LBRT_FP16_SHIFTED) &&
          (nb == 56 || nb == 112);
 }
 

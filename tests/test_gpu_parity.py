@@ -291,15 +291,24 @@ def test_sphere_fp64_full_length():
                                   wl.BC_OUTFLOW, wl.BC_OUTFLOW), 4, wl.COLL_IMPLICIT, 0.0),
     ("fp16", 50, (9, 11, 70), (wl.BC_PERIODIC,) * 6, 0, wl.COLL_IMPLICIT, 0.0),
     ("bf16", 50, (10, 12, 134), (wl.BC_OUTFLOW,) * 6, 0, wl.COLL_IMPLICIT, 0.4),
+    ("bf16s", 110, (12, 16, 140), (wl.BC_INFLOW, wl.BC_OUTFLOW, wl.BC_INFLOW, wl.BC_OUTFLOW,
+                                   wl.BC_INFLOW, wl.BC_OUTFLOW), 6, wl.COLL_IMPLICIT, 0.0),
+    ("fp16s", 50, (9, 11, 70), (wl.BC_PERIODIC,) * 6, 0, wl.COLL_IMPLICIT, 0.3),
+    ("bf16s", 50, (8, 10, 136), (wl.BC_PERIODIC, wl.BC_PERIODIC, wl.BC_OUTFLOW, wl.BC_INFLOW,
+                                 wl.BC_PERIODIC, wl.BC_PERIODIC), 3, wl.COLL_LAMBDA, 0.5),
+    ("fp16s", 110, (7, 9, 266), (wl.BC_OUTFLOW,) * 6, 0, wl.COLL_EXPLICIT, -0.25),
 ])
 def test_pair_kernel_equals_main_kernel(storage, npoints, shape, bc, planes, coll, lam):
     """The interior on the two-cells-per-lane kernel (x in [2, nx - 2), the
     face columns on the checked path) against the one-cell-per-lane main
     kernel: the same populations, E and F bit for bit (with the same
-    stochastic rounding bits).  The diagnostics are sums in a
+    stochastic rounding bits), for plain and equilibrium-shifted 16-bit
+    storage (the shifted state's E array included).  The diagnostics are
+    sums in a
     different grouping: the energy sums (FP64 per lane) to 1e-12, the face
     fluxes (FP32 per lane over a block's z range, then FP64) to 1e-6."""
-    st = {"bf16": L().LBRT_BF16, "fp16": L().LBRT_FP16}[storage]
+    st = {"bf16": L().LBRT_BF16, "fp16": L().LBRT_FP16, "bf16s": L().LBRT_BF16_SHIFTED,
+          "fp16s": L().LBRT_FP16_SHIFTED}[storage]
     p = wl.random_problem(91, shape=shape, npoints=npoints, bc=bc, inflow_planes=planes,
                           collision=coll, lam=lam, steps=3,
                           kappa_range=(-2.0, 2.0) if coll == wl.COLL_IMPLICIT else (-2.0, 0.0))
