@@ -665,7 +665,7 @@ step_kernel_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *_
                  const DirTab<float> *__restrict__ dtab, const InflowArgs *__restrict__ inflow,
                  const KParams p, float *__restrict__ Eout, float *__restrict__ Fout,
                  double *__restrict__ partials) {
-  const int t = xcd_tile(blockIdx.x, p.nblocks);
+  const int t = xcd_tile(blockIdx.x, p.ntx * p.main_nty);
   const int tix = t % p.ntx;
   const int r = t / p.ntx;
   const int y = p.main_ty0 + r % p.main_nty;
