@@ -1,8 +1,9 @@
 """GPU parity at the full workload sizes, in the launch configuration that
 bench.py times (default tiling, inflow ghosts, E, F and FP64 diagnostics on):
 
-* crossing beams + opaque sphere, 256^3 x 110 directions, FP32 and BF16
-  storage, one step from a seeded random state, checked against the FP64
+* crossing beams + opaque sphere, 256^3 x 110 directions, FP32, BF16 and
+  equilibrium-shifted BF16 storage, one step from a seeded random state,
+  checked against the FP64
   oracle's one-step update at sampled cells (interior, faces, edges,
   corners, tile and z-range seams, both beam footprints, the sphere);
 * the moving-fluid shear flow, 192^3 x 146, one step, same check;
@@ -56,6 +57,22 @@ def _random_state(prob, seed):
     return I0
 
 
+class _Shifted:
+    """Directions of an equilibrium-shifted state, s_i d_i + w_i E, as
+    float64 values on demand."""
+
+    def __init__(self, q16, E, weights, scale):
+        self.q16, self.E, self.w, self.scale = q16, E.astype(np.float64), weights, scale
+        self._i, self._v = None, None
+
+    def __getitem__(self, i):
+        if i != self._i:
+            self._i = i
+            self._v = (self.q16[i].float().double().numpy() * float(self.scale[i])
+                       + float(self.w[i]) * self.E)
+        return self._v
+
+
 class _Scaled:
     """Directions of a reduced-storage state as float64 values on demand."""
 
@@ -90,7 +107,7 @@ def _gather(ctx, prob, out, E, F, cells, storage):
     L = gh.lib()
     idx = torch.as_tensor(cells[:, 0] * prob.ny * prob.nx + cells[:, 1] * prob.nx + cells[:, 2],
                           device="cuda")
-    if storage in (L.LBRT_BF16, L.LBRT_FP16):
+    if storage in (L.LBRT_BF16, L.LBRT_FP16, L.LBRT_BF16_SHIFTED, L.LBRT_FP16_SHIFTED):
         dec = torch.empty(prob.ndir * prob.ncell, dtype=torch.float32, device="cuda")
         L.lbrt_convert(ctx, out, storage, dec, L.LBRT_FP32)
         out = dec
@@ -174,6 +191,53 @@ def test_beams_256_bf16_sampled_cells():
     # a few FP32 roundings; E and F (from the FP32 collision) to the
     # precision-form bound
     _check(prob, I_gpu, E_gpu, F_gpu, ref, 2.0 ** -7 * (1 + 1e-4), 2e-3)
+
+
+def test_beams_256_bf16_shifted_sampled_cells():
+    """The equilibrium-shifted BF16 form (the pair kernel with its E
+    staging, at the bench's launch configuration): a seeded state of cell
+    energies E ~ U(0.5, 1.5) (FP32) and stored deviations d_i ~ U(-0.5, 0.5)
+    (BF16), so I_i = w_i (d_i + E).  Bounds, element by element: the stored
+    new deviation is one stochastic rounding of (I_i' - w_i E') / w_i to BF16,
+    within one unit in its last place, so |I_i - ref_i| <= 2^-7 |ref_i -
+    w_i E_ref| plus FP32 slack (1e-5 of the cell's largest population); E'
+    and F' are formed in FP32 before any rounding: 1e-5, as for FP32 storage."""
+    torch = gh.torch_mod()
+    L = gh.lib()
+    st = L.LBRT_BF16_SHIFTED
+    prob = wl.beams(n=256, alloc_state=False)
+    print(prob.name, prob.shape, prob.ndir, "bf16 shifted", flush=True)
+    w = np.asarray(prob.weights, dtype=np.float64)
+    scale = np.abs(w)
+    g = torch.Generator().manual_seed(2028)
+    Ecell = (0.5 + torch.rand(prob.shape, generator=g)).numpy().astype(np.float32)
+    q16 = torch.empty((prob.ndir,) + prob.shape, dtype=torch.bfloat16)
+    for i in range(prob.ndir):
+        q16[i] = (torch.rand(prob.shape, generator=g) - 0.5).to(torch.bfloat16)
+    nbytes = L.state_bytes(st, prob.ndir, prob.ncell)
+    state = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    state[:2 * prob.ndir * prob.ncell] = q16.reshape(-1).view(torch.uint8).cuda()
+    off = L.state_e_offset(st, prob.ndir, prob.ncell)
+    state[off:off + 4 * prob.ncell] = torch.from_numpy(Ecell.reshape(-1)).view(torch.uint8).cuda()
+    ctx, out, E, F = _gpu_step(prob, state, st)
+    del state
+    cells = _sample_cells(prob, np.random.default_rng(8), extra=_beam_cells(prob))
+    I_gpu, E_gpu, F_gpu = _gather(ctx, prob, out, E, F, cells, st)
+    del out, E, F
+    ctx.close()
+    torch.cuda.empty_cache()
+    ref = orc.step_cells(_Shifted(q16, Ecell, w, scale), prob, cells)
+    E_ref = ref.sum(axis=0)
+    F_ref = prob.dirs.T @ ref
+    dev = np.abs(ref - w[:, None] * E_ref[None, :])
+    bound = 2.0 ** -7 * dev + 1e-5 * np.max(np.abs(ref), axis=0)[None, :]
+    excess = np.max(np.abs(I_gpu - ref) / bound)
+    err_E = np.max(np.abs(E_gpu - E_ref) / np.abs(E_ref))
+    err_F = np.max(np.abs(F_gpu - F_ref)) / np.max(np.abs(F_ref))
+    print(f"{len(cells)} cells: max |I - ref| / bound {excess:.3f}, max rel err E {err_E:.2e}, "
+          f"F {err_F:.2e}", flush=True)
+    assert excess <= 1.0
+    assert err_E < 1e-5 and err_F < 1e-5
 
 
 def test_moving_192_fp32_sampled_cells():

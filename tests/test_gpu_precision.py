@@ -17,6 +17,9 @@ max |got - ref| / max |ref|.  Bounds:
   bilinear pull averages the errors of neighbouring cells, which keeps the
   accumulated error near u (measured: 4.6e-3) rather than growing with the
   number of steps.
+* The equilibrium-shifted forms take the bounds of their formats: in a beam
+  cell the deviation from w_i E is the population itself, so the shift
+  neither helps nor hurts there.
 """
 import os
 
@@ -48,10 +51,13 @@ def _errors(E, F, ref):
     ("fp32", 1e-5, 1e-5),
     ("fp16", 2e-3, None),
     ("bf16", 2.0 ** -7, None),
+    ("fp16s", 2e-3, None),
+    ("bf16s", 2.0 ** -7, None),
 ])
 def test_beams64_500_steps_against_oracle(storage, tol_l2, tol_max):
     L = gh.lib()
-    st = {"fp32": L.LBRT_FP32, "fp16": L.LBRT_FP16, "bf16": L.LBRT_BF16}[storage]
+    st = {"fp32": L.LBRT_FP32, "fp16": L.LBRT_FP16, "bf16": L.LBRT_BF16,
+          "fp16s": L.LBRT_FP16_SHIFTED, "bf16s": L.LBRT_BF16_SHIFTED}[storage]
     ref = np.load(GOLDEN)
     prob = wl.beams(n=int(ref["n"]), steps=int(ref["steps"]))
     print(prob.name, prob.shape, prob.ndir, prob.steps, storage, flush=True)
