@@ -33,9 +33,11 @@
 // and last pair are face pairs, whose neighbouring pair for sx > 0 (first)
 // or sx < 0 (last) is a ghost: the lane loads its own pair in its place and
 // zeroes it; an inflow ghost plane on the face is added afterwards
-// (x_ghost_correction, as on the other paths).  The zeroing is two selects
-// per slot on every tile (a second copy of the slot loop for the face tiles
-// only would run the kernel out of scalar registers).  The x-face outflux of
+// (x_ghost_correction, as on the other paths).  The zeroing is two ANDs per
+// slot on every tile, with a per-lane mask picked by the slot's sign (a
+// second copy of the slot loop for the face tiles only would run the kernel
+// out of scalar registers; per-slot selects on the face flags cost three
+// more VALU instructions per slot, 1-2 % of the step).  The x-face outflux of
 // the face cells is booked after each plane from their own values parked in
 // LDS, one slot per lane.  With periodic x the tiles compute
 // x in [2, nx - 2) and the columns x < 2, x >= nx - 2 are tiles of the
@@ -311,10 +313,14 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
       if constexpr (SH) fxb = fma(bfE, estage[dzn ? b1 : b0][eix], fxb);
     }
   };
+  // per lane: all ones, or zero where the neighbouring pair of a slot with
+  // sx > 0 (kpos) / sx < 0 (kneg) is a ghost; a slot selects one with its
+  // uniform sign and masks the neighbour's dwords (one AND each)
+  const uint32_t kpos = lox ? 0u : ~0u, kneg = hix ? 0u : ~0u;
   auto zap = [&](const PairTab &d, R (&v)[4]) {
-    const bool z0 = (d.flags & kPairSxPos) ? lox : hix;
-    v[1] = z0 ? R(0) : v[1];
-    v[3] = z0 ? R(0) : v[3];
+    const uint32_t k = (d.flags & kPairSxPos) ? kpos : kneg;
+    v[1] &= k;
+    v[3] &= k;
   };
 
   // Shifted storage: every slot of a plane interpolates E at the tile's
@@ -375,7 +381,11 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
     const f32x2 a = *reinterpret_cast<const f32x2 *>(eb + eown);
     const f32x2 b = *reinterpret_cast<const f32x2 *>(eb + eown + ys);
     T an = eb[eown + nbo], bn = eb[eown + ys + nbo];
-    if (pos ? lox : hix) an = bn = T(0);
+    {
+      const uint32_t k = pos ? kpos : kneg;
+      an = __uint_as_float(__float_as_uint(an) & k);
+      bn = __uint_as_float(__float_as_uint(bn) & k);
+    }
     PElo = interp4w(d, a.x, pos ? an : a.y, b.x, pos ? bn : b.y);
     PEhi = interp4w(d, a.y, pos ? a.x : an, b.y, pos ? b.x : bn);
   };
@@ -529,7 +539,7 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
         if ((xgmask >> J) & 1u) {
           const DirTab<T> &d = dtab[q * M + J];
           const bool pos = d.s[0] > 0;
-          if (pos ? lox : hix) {
+          if ((pos ? kpos : kneg) == 0u) {
             const T dI = x_ghost_correction<T>(d, inflow->ghost[q * M + J][0], y, z, p.ny, nz,
                                                p.periodic[1], perz);
             fin += (double)dI;
