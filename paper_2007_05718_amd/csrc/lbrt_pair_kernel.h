@@ -627,13 +627,15 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
       g0 = cell_hash(cell0 ^ p.seed);
       g1 = cell_hash((cell0 + 1u) ^ p.seed);
     }
-    if (valid) {
+    // one copy of the slot loop per (lambda = 0, stochastic rounding) pair,
+    // so that no slot branches on them
+    auto collide_all = [&]<bool LZ, bool SR>() {
 #pragma unroll
       for (int jj = 0; jj < M; ++jj) {
         const PairColl &d = tbc[jj];
         if (d.inv_scale != T(0)) {   // a direction (padding slots carry 0)
-          T o0v = collide_pair(d, c2.x, a2.x, b0.x, b1.x, b2.x, Is[jj][0], lamzero);
-          T o1v = collide_pair(d, c2.y, a2.y, b0.y, b1.y, b2.y, Is[jj][1], lamzero);
+          T o0v = collide_pair(d, c2.x, a2.x, b0.x, b1.x, b2.x, Is[jj][0], LZ);
+          T o1v = collide_pair(d, c2.y, a2.y, b0.y, b1.y, b2.y, Is[jj][1], LZ);
           if constexpr (SH) {
             // stored: the deviation from w_i E'
             o0v = fma(-d.w, en2.x, o0v);
@@ -643,8 +645,21 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
             o0v *= d.inv_scale;
             o1v *= d.inv_scale;
           }
-          IO::st(outz + d.plane_off, ost, o0v, o1v, g0 ^ d.rnd, g1 ^ d.rnd, stoch);
+          IO::st(outz + d.plane_off, ost, o0v, o1v, g0 ^ d.rnd, g1 ^ d.rnd, SR);
         }
+      }
+    };
+    if (valid) {
+      if (lamzero) {
+        if (stoch)
+          collide_all.template operator()<true, true>();
+        else
+          collide_all.template operator()<true, false>();
+      } else {
+        if (stoch)
+          collide_all.template operator()<false, true>();
+        else
+          collide_all.template operator()<false, false>();
       }
     }
     // this plane's x-face outflux (own values parked during the slot loop;
