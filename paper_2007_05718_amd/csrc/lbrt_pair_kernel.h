@@ -633,7 +633,7 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
 #pragma unroll
       for (int jj = 0; jj < M; ++jj) {
         const PairColl &d = tbc[jj];
-        if (d.inv_scale != T(0)) {   // a direction (padding slots carry 0)
+        if (q * M + jj < p.ndir) {   // a direction (null slots come last)
           T o0v = collide_pair(d, c2.x, a2.x, b0.x, b1.x, b2.x, Is[jj][0], LZ);
           T o1v = collide_pair(d, c2.y, a2.y, b0.y, b1.y, b2.y, Is[jj][1], LZ);
           if constexpr (SH) {

@@ -1160,7 +1160,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
 #pragma unroll
           for (int j = 0; j < M; ++j) {
             const DirTab<T> &d = tbc[j];
-            if (d.active)
+            if (q * M + j < p.ndir)   // a direction (null slots come last)
               sto_sr<S>(outz + d.plane_off, ost,
                         shift(d, collide_one(d, c, alpha, be0, be1, be2, Is[j], lz)) *
                             d.inv_scale,
@@ -1170,7 +1170,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
 #pragma unroll
           for (int j = 0; j < M; ++j) {
             const DirTab<T> &d = tbc[j];
-            if (d.active) {
+            if (q * M + j < p.ndir) {
               T o = shift(d, collide_one(d, c, alpha, be0, be1, be2, Is[j], true));
               if (Tr::kReduced) o *= d.inv_scale;
               sto<S>(outz + d.plane_off, ost, o);
@@ -1180,7 +1180,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
 #pragma unroll
           for (int j = 0; j < M; ++j) {
             const DirTab<T> &d = tbc[j];
-            if (d.active) {
+            if (q * M + j < p.ndir) {
               T o = shift(d, collide_one(d, c, alpha, be0, be1, be2, Is[j], false));
               if (Tr::kReduced) o *= d.inv_scale;
               sto<S>(outz + d.plane_off, ost, o);
@@ -1208,7 +1208,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
 #pragma unroll
         for (int j = 0; j < M; ++j) {
           const DirTab<T> &d = tbc[j];
-          if (d.active) {
+          if (q * M + j < p.ndir) {
             const T D = T(1) - (vx * d.n[0] + vy * d.n[1] + vz * d.n[2]);
             const T a = rcp<T>(fma(dtWk, D, T(1)));
             const T iD = rcp<T>(D);
