@@ -481,6 +481,7 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
 
   for (int z = zb; z < ze; ++z) {
     tb = tab + opaque(q * M);
+    const int nv = opaque(p.ndir - q * M);   // this wave's direction slots
     const int64_t cz = (int64_t)z * pc;
     const T kat = med[0], kst = med[1], et = med[2];
     const int64_t cz_next = z + 1 < ze ? cz + pc : cz;
@@ -633,7 +634,7 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
 #pragma unroll
       for (int jj = 0; jj < M; ++jj) {
         const PairColl &d = tbc[jj];
-        if (q * M + jj < p.ndir) {   // a direction (null slots come last)
+        if (jj < nv) {   // a direction (null slots come last)
           T o0v = collide_pair(d, c2.x, a2.x, b0.x, b1.x, b2.x, Is[jj][0], LZ);
           T o1v = collide_pair(d, c2.y, a2.y, b0.y, b1.y, b2.y, Is[jj][1], LZ);
           if constexpr (SH) {

@@ -936,6 +936,9 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
   for (int z = zb; z < ze; ++z) {
     const int par = (z - zb) & 1;
     tb = tab + opaque(q * M);
+    // this wave's slots that hold directions (null slots come last), opaque
+    // per plane so that the per-slot tests are not hoisted as lane masks
+    const int nv = opaque(p.ndir - q * M);
     const int64_t cz = (int64_t)z * pc;
 
     // this plane's medium, loaded during the previous plane; the next
@@ -1160,7 +1163,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
 #pragma unroll
           for (int j = 0; j < M; ++j) {
             const DirTab<T> &d = tbc[j];
-            if (q * M + j < p.ndir)   // a direction (null slots come last)
+            if (j < nv)   // a direction (null slots come last)
               sto_sr<S>(outz + d.plane_off, ost,
                         shift(d, collide_one(d, c, alpha, be0, be1, be2, Is[j], lz)) *
                             d.inv_scale,
@@ -1170,7 +1173,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
 #pragma unroll
           for (int j = 0; j < M; ++j) {
             const DirTab<T> &d = tbc[j];
-            if (q * M + j < p.ndir) {
+            if (j < nv) {
               T o = shift(d, collide_one(d, c, alpha, be0, be1, be2, Is[j], true));
               if (Tr::kReduced) o *= d.inv_scale;
               sto<S>(outz + d.plane_off, ost, o);
@@ -1180,7 +1183,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
 #pragma unroll
           for (int j = 0; j < M; ++j) {
             const DirTab<T> &d = tbc[j];
-            if (q * M + j < p.ndir) {
+            if (j < nv) {
               T o = shift(d, collide_one(d, c, alpha, be0, be1, be2, Is[j], false));
               if (Tr::kReduced) o *= d.inv_scale;
               sto<S>(outz + d.plane_off, ost, o);
@@ -1208,7 +1211,7 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
 #pragma unroll
         for (int j = 0; j < M; ++j) {
           const DirTab<T> &d = tbc[j];
-          if (q * M + j < p.ndir) {
+          if (j < nv) {
             const T D = T(1) - (vx * d.n[0] + vy * d.n[1] + vz * d.n[2]);
             const T a = rcp<T>(fma(dtWk, D, T(1)));
             const T iD = rcp<T>(D);
