@@ -630,11 +630,11 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
     }
     // one copy of the slot loop per (lambda = 0, stochastic rounding) pair,
     // so that no slot branches on them
-    auto collide_all = [&]<bool LZ, bool SR>() {
+    auto collide_all = [&]<bool LZ, bool SR, bool FULL>() {
 #pragma unroll
       for (int jj = 0; jj < M; ++jj) {
         const PairColl &d = tbc[jj];
-        if (jj < nv) {   // a direction (null slots come last)
+        if (FULL || jj < nv) {   // a direction (null slots come last)
           T o0v = collide_pair(d, c2.x, a2.x, b0.x, b1.x, b2.x, Is[jj][0], LZ);
           T o1v = collide_pair(d, c2.y, a2.y, b0.y, b1.y, b2.y, Is[jj][1], LZ);
           if constexpr (SH) {
@@ -650,17 +650,23 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
         }
       }
     };
+    auto collide_w = [&]<bool LZ, bool SR>() {
+      if (nv >= M)
+        collide_all.template operator()<LZ, SR, true>();
+      else
+        collide_all.template operator()<LZ, SR, false>();
+    };
     if (valid) {
       if (lamzero) {
         if (stoch)
-          collide_all.template operator()<true, true>();
+          collide_w.template operator()<true, true>();
         else
-          collide_all.template operator()<true, false>();
+          collide_w.template operator()<true, false>();
       } else {
         if (stoch)
-          collide_all.template operator()<false, true>();
+          collide_w.template operator()<false, true>();
         else
-          collide_all.template operator()<false, false>();
+          collide_w.template operator()<false, false>();
       }
     }
     // this plane's x-face outflux (own values parked during the slot loop;

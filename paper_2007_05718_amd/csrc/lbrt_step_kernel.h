@@ -1158,37 +1158,40 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
           if constexpr (SH) return (T)fma(-d.w, En, o);
           return o;
         };
+        // one copy of the slot loop per (stochastic rounding, lambda = 0)
+        // case and per whether the wave has null slots, so that no slot
+        // branches on them
+        auto store_all = [&]<bool SR, bool LZ, bool FULL>() {
+          const uint32_t gr = SR ? cell_hash((uint32_t)(cz + ocell) ^ p.seed) : 0u;
+#pragma unroll
+          for (int j = 0; j < M; ++j) {
+            const DirTab<T> &d = tbc[j];
+            if (FULL || j < nv) {   // a direction (null slots come last)
+              T o = shift(d, collide_one(d, c, alpha, be0, be1, be2, Is[j], LZ));
+              if constexpr (SR) {
+                sto_sr<S>(outz + d.plane_off, ost, o * d.inv_scale, gr ^ d.rnd);
+              } else {
+                if (Tr::kReduced) o *= d.inv_scale;
+                sto<S>(outz + d.plane_off, ost, o);
+              }
+            }
+          }
+        };
+        auto store_w = [&]<bool SR, bool LZ>() {
+          if (nv >= M)
+            store_all.template operator()<SR, LZ, true>();
+          else
+            store_all.template operator()<SR, LZ, false>();
+        };
         if (Tr::kReduced && (p.flags & KF_STOCH)) {
-          const uint32_t gr = cell_hash((uint32_t)(cz + ocell) ^ p.seed);
-#pragma unroll
-          for (int j = 0; j < M; ++j) {
-            const DirTab<T> &d = tbc[j];
-            if (j < nv)   // a direction (null slots come last)
-              sto_sr<S>(outz + d.plane_off, ost,
-                        shift(d, collide_one(d, c, alpha, be0, be1, be2, Is[j], lz)) *
-                            d.inv_scale,
-                        gr ^ d.rnd);
-          }
+          if (lz)
+            store_w.template operator()<true, true>();
+          else
+            store_w.template operator()<true, false>();
         } else if (lz) {
-#pragma unroll
-          for (int j = 0; j < M; ++j) {
-            const DirTab<T> &d = tbc[j];
-            if (j < nv) {
-              T o = shift(d, collide_one(d, c, alpha, be0, be1, be2, Is[j], true));
-              if (Tr::kReduced) o *= d.inv_scale;
-              sto<S>(outz + d.plane_off, ost, o);
-            }
-          }
+          store_w.template operator()<false, true>();
         } else {
-#pragma unroll
-          for (int j = 0; j < M; ++j) {
-            const DirTab<T> &d = tbc[j];
-            if (j < nv) {
-              T o = shift(d, collide_one(d, c, alpha, be0, be1, be2, Is[j], false));
-              if (Tr::kReduced) o *= d.inv_scale;
-              sto<S>(outz + d.plane_off, ost, o);
-            }
-          }
+          store_w.template operator()<false, false>();
         }
       }
     } else {
