@@ -151,11 +151,25 @@ constexpr int kPairSPos = 3 * kPairSRow;
 constexpr int kPairSBuf = kPairSPos + 2;
 
 // Slots whose four row loads (4 VGPRs) are in flight ahead of the slot being
-// interpolated: 4, and 2 for shifted storage, whose E taps and staging take
-// the registers of two (with 3 it needs 133 VGPRs: one block per CU).
+// interpolated.  Two 8-wave blocks per CU need at most 128 VGPRs: BF16 keeps
+// 4 ahead (127 VGPRs; 3 ahead measured 3 % slower); FP16, whose conversions
+// take a few more registers, 3 (4 needs 129: one block per CU, 1.5x the
+// time; bounded to 128 it spills and is 7 % slower than 3 ahead); shifted
+// storage 2, its E taps and staging taking the registers of two.
 template <typename S>
 constexpr int pair_pf_depth(int m) {
-  return StoreTraits<S>::kShifted ? (m < 2 ? m : 2) : (m < 4 ? m : 4);
+  const int d = StoreTraits<S>::kShifted ? 2 : (std::is_same_v<S, f16_t> ? 3 : 4);
+  return m < d ? m : d;
+}
+
+// Waves per SIMD the pair kernel is bounded for (a VGPR cap of 512 / w).  The
+// shifted 56-slot kernels (four waves, each staging two E cells per lane and
+// combining two sums) need 133 VGPRs unbounded; bounded to 128 they spill
+// 12 bytes per lane and run 5 % faster than at three waves per SIMD.  The
+// others fit 128 unbounded (a bound makes the allocator spill).
+template <typename S, int NB>
+constexpr int pair_waves_per_simd() {
+  return (StoreTraits<S>::kShifted && NB == 56) ? 4 : waves_per_simd<S>(NB);
 }
 
 // Plane value from four taps with the slot's per-axis weights: the same
@@ -630,11 +644,11 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
     }
     // one copy of the slot loop per (lambda = 0, stochastic rounding) pair,
     // so that no slot branches on them
-    auto collide_all = [&]<bool LZ, bool SR, bool FULL>() {
+    auto collide_all = [&]<bool LZ, bool SR>() {
 #pragma unroll
       for (int jj = 0; jj < M; ++jj) {
         const PairColl &d = tbc[jj];
-        if (FULL || jj < nv) {   // a direction (null slots come last)
+        if (jj < nv) {   // a direction (null slots come last)
           T o0v = collide_pair(d, c2.x, a2.x, b0.x, b1.x, b2.x, Is[jj][0], LZ);
           T o1v = collide_pair(d, c2.y, a2.y, b0.y, b1.y, b2.y, Is[jj][1], LZ);
           if constexpr (SH) {
@@ -650,23 +664,17 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
         }
       }
     };
-    auto collide_w = [&]<bool LZ, bool SR>() {
-      if (nv >= M)
-        collide_all.template operator()<LZ, SR, true>();
-      else
-        collide_all.template operator()<LZ, SR, false>();
-    };
     if (valid) {
       if (lamzero) {
         if (stoch)
-          collide_w.template operator()<true, true>();
+          collide_all.template operator()<true, true>();
         else
-          collide_w.template operator()<true, false>();
+          collide_all.template operator()<true, false>();
       } else {
         if (stoch)
-          collide_w.template operator()<false, true>();
+          collide_all.template operator()<false, true>();
         else
-          collide_w.template operator()<false, false>();
+          collide_all.template operator()<false, false>();
       }
     }
     // this plane's x-face outflux (own values parked during the slot loop;
@@ -690,7 +698,7 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
 
 // Interior tiles of 128 cells, in the XCD-aware block order of the main kernel.
 template <typename S, int NB>
-__global__ void __launch_bounds__(64 * waves_for(NB), waves_per_simd<S>(NB))
+__global__ void __launch_bounds__(64 * waves_for(NB), (pair_waves_per_simd<S, NB>()))
 step_kernel_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__ ka,
                  const float *__restrict__ ks, const float *__restrict__ eta,
                  const PairTab *__restrict__ tab, const PairColl *__restrict__ ctab,
