@@ -394,16 +394,18 @@ checked_P(const DirTab<typename StoreTraits<S>::T> &d, const S *__restrict__ pl,
     gx[b] = cx;
     v[b] = Tr::ld(pl + (inb[b] ? (int64_t)cy * nx + cx : 0));
   }
+  // Out-of-box taps, by selects (no per-lane branches): a slot with a
+  // y-face ghost plane reads its four ghost values at clamped columns.
+  T g[4] = {T(0), T(0), T(0), T(0)};
+  if (gy != nullptr) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      g[b] = (T)gload(gy, (int64_t)zl * nx + min(max(gx[b], 0), nx - 1));
+  }
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
-    if (!inb[b]) {
-      T val = T(0);
-      if (yg[b]) {
-        const T gv = (T)gload(gy, (int64_t)zl * nx + gx[b]);
-        val = Tr::kReduced ? gv * d.inv_scale : gv;
-      }
-      v[b] = val;
-    }
+    const T gv = Tr::kReduced ? g[b] * d.inv_scale : g[b];
+    v[b] = inb[b] ? v[b] : (yg[b] ? gv : T(0));
   }
   own = v[0];
   return interp4(d, v[0], v[1], v[2], v[3]);
@@ -722,7 +724,8 @@ march(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restrict__
     if constexpr (SH)
       PE = checked_PE<T>(d, reinterpret_cast<const float *>(ein_bytes) + (int64_t)zl * pc, x, y,
                          valid, nx, ny, perx, pery, ownE);
-    if (diag && book && face_tile && valid) {
+    // (an invalid lane has no face flags set and books 0)
+    if (diag && book && face_tile) {
       T fz = T(0);
       T ownp = Tr::kReduced ? own * d.scale : own;
       if constexpr (SH) ownp = fma(d.w, ownE, ownp);
