@@ -154,22 +154,25 @@ constexpr int kPairSBuf = kPairSPos + 2;
 // interpolated.  Two 8-wave blocks per CU need at most 128 VGPRs: BF16 keeps
 // 4 ahead (127 VGPRs; 3 ahead measured 3 % slower); FP16, whose conversions
 // take a few more registers, 3 (4 needs 129: one block per CU, 1.5x the
-// time; bounded to 128 it spills and is 7 % slower than 3 ahead); shifted
-// storage 2, its E taps and staging taking the registers of two.
-template <typename S>
+// time; bounded to 128 it spills and is 7 % slower than 3 ahead).  Shifted
+// storage, whose E taps and staging take more registers, is bounded to 128
+// VGPRs (below) and keeps 3 ahead with 112 slots (28 bytes of spill per
+// lane, 3.5 % faster than 2 ahead), 2 with 56 (3 was 2 % slower).
+template <typename S, int NB>
 constexpr int pair_pf_depth(int m) {
-  const int d = StoreTraits<S>::kShifted ? 2 : (std::is_same_v<S, f16_t> ? 3 : 4);
+  const int d = StoreTraits<S>::kShifted ? (NB >= 112 ? 3 : 2)
+                                         : (std::is_same_v<S, f16_t> ? 3 : 4);
   return m < d ? m : d;
 }
 
-// Waves per SIMD the pair kernel is bounded for (a VGPR cap of 512 / w).  The
-// shifted 56-slot kernels (four waves, each staging two E cells per lane and
-// combining two sums) need 133 VGPRs unbounded; bounded to 128 they spill
-// 12 bytes per lane and run 5 % faster than at three waves per SIMD.  The
-// others fit 128 unbounded (a bound makes the allocator spill).
+// Waves per SIMD the pair kernel is bounded for (a VGPR cap of 512 / w).
+// The shifted kernels exceed 128 VGPRs unbounded (133 with 56 slots and 2
+// ahead, where the bound costs 12 bytes of spill and runs 5 % faster than
+// three waves per SIMD).  The others fit 128 unbounded (a bound makes the
+// allocator spill).
 template <typename S, int NB>
 constexpr int pair_waves_per_simd() {
-  return (StoreTraits<S>::kShifted && NB == 56) ? 4 : waves_per_simd<S>(NB);
+  return StoreTraits<S>::kShifted ? 4 : waves_per_simd<S>(NB);
 }
 
 // Plane value from four taps with the slot's per-axis weights: the same
@@ -203,7 +206,7 @@ march_pair(const S *__restrict__ Iin, S *__restrict__ Iout, const float *__restr
   constexpr int NC = 128;                       // cells of a tile
   constexpr int RI = 4 * NC / (64 * NW);        // combine items per lane
   static_assert(4 * NC % (64 * NW) == 0, "combine items must split evenly");
-  constexpr int D = pair_pf_depth<S>(M);
+  constexpr int D = pair_pf_depth<S, NB>(M);
 
   const int nx = p.nx, nz = p.nz;
   const int64_t pc = (int64_t)nx * p.ny;
