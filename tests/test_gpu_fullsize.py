@@ -1,8 +1,8 @@
 """GPU parity at the full workload sizes, in the launch configuration that
 bench.py times (default tiling, inflow ghosts, E, F and FP64 diagnostics on):
 
-* crossing beams + opaque sphere, 256^3 x 110 directions, FP32, BF16 and
-  equilibrium-shifted BF16 storage, one step from a seeded random state,
+* crossing beams + opaque sphere, 256^3 x 110 directions, FP32, BF16, FP16
+  and equilibrium-shifted BF16 storage, one step from a seeded random state,
   checked against the FP64
   oracle's one-step update at sampled cells (interior, faces, edges,
   corners, tile and z-range seams, both beam footprints, the sphere);
@@ -166,31 +166,34 @@ def test_beams_256_fp32_sampled_cells(scatter):
     _check(prob, I_gpu, E_gpu, F_gpu, ref, 1e-5, 1e-5)
 
 
-def test_beams_256_bf16_sampled_cells():
+@pytest.mark.parametrize("fmt", ["bf16", "fp16"])
+def test_beams_256_16bit_sampled_cells(fmt):
     torch = gh.torch_mod()
     L = gh.lib()
+    st, tdt, p = {"bf16": (L.LBRT_BF16, torch.bfloat16, 8), "fp16": (L.LBRT_FP16, torch.float16, 11)}[fmt]
     prob = wl.beams(n=256, alloc_state=False)
-    print(prob.name, prob.shape, prob.ndir, "bf16", flush=True)
+    print(prob.name, prob.shape, prob.ndir, fmt, flush=True)
     scale = np.abs(prob.weights)
     g = torch.Generator().manual_seed(2027)
-    q16 = torch.empty((prob.ndir,) + prob.shape, dtype=torch.bfloat16)
+    q16 = torch.empty((prob.ndir,) + prob.shape, dtype=tdt)
     for i in range(prob.ndir):       # stored values U(0, 1): I_i = w_i q
-        q16[i] = torch.rand(prob.shape, generator=g).to(torch.bfloat16)
+        q16[i] = torch.rand(prob.shape, generator=g).to(tdt)
     state = q16.reshape(-1).cuda()
-    ctx, out, E, F = _gpu_step(prob, state, L.LBRT_BF16)
+    ctx, out, E, F = _gpu_step(prob, state, st)
     del state
     cells = _sample_cells(prob, np.random.default_rng(6), extra=_beam_cells(prob))
-    I_gpu, E_gpu, F_gpu = _gather(ctx, prob, out, E, F, cells, L.LBRT_BF16)
+    I_gpu, E_gpu, F_gpu = _gather(ctx, prob, out, E, F, cells, st)
     del out, E, F
     ctx.close()
     torch.cuda.empty_cache()
     ref = orc.step_cells(_Scaled(q16, scale), prob, cells)
-    # one stochastic rounding of each stored value to BF16 (8 significant
-    # bits) picks one of the two neighbouring BF16 values, so it is within one
-    # unit in the last place, 2^-7 of a value just above a power of two, plus
-    # a few FP32 roundings; E and F (from the FP32 collision) to the
+    # one stochastic rounding of each stored value to the format (p
+    # significant bits: 8 for BF16, 11 for FP16) picks one of the two
+    # neighbouring representable values, so it is within one unit in the
+    # last place, 2^(1 - p) of a value just above a power of two, plus a few
+    # FP32 roundings; E and F (from the FP32 collision) to the
     # precision-form bound
-    _check(prob, I_gpu, E_gpu, F_gpu, ref, 2.0 ** -7 * (1 + 1e-4), 2e-3)
+    _check(prob, I_gpu, E_gpu, F_gpu, ref, 2.0 ** (1 - p) * (1 + 1e-4), 2e-3)
 
 
 def test_beams_256_bf16_shifted_sampled_cells():
