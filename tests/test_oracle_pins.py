@@ -312,6 +312,28 @@ def test_lambda_moments_follow_geometric_recursion():
         assert np.max(np.abs(E / ref - 1)) < 1e-13
 
 
+@pytest.mark.parametrize("lam", [0.5, -0.9])
+def test_lambda_flux_follows_geometric_recursion(lam):
+    """With lambda != 0 each cycle maps F -> c (F* + dt k0 lam F / 3) (the
+    rule integrates n n^T to I / 3 and n to 0), so at a finite cycle count
+    F_K = F_inf + (F* - F_inf) a^K with a = c dt k0 lam / 3 and
+    F_inf = c F* / (1 - a); E follows the lambda = 0 recursion unchanged."""
+    dirs, w, Istar, ka, k0, eta = _random_collision_inputs(50, kmax=1)
+    dt = 0.5
+    Es, Fs = orc.moments(Istar, dirs)
+    c = 1 / (1 + dt * (k0 + ka))
+    a = c * dt * k0 * lam / 3
+    Finf = c * Fs / (1 - a)
+    Einf = (Es + dt * eta) / (1 + dt * ka)
+    for K in (1, 2, 3, 5):
+        _, E, F = orc.collide_lambda(Istar, dirs, w, ka, k0, eta, dt, lam, cycles=K,
+                                     return_moments=True)
+        Fref = Finf + (Fs - Finf) * a ** K
+        assert np.all(np.abs(F - Fref) < 1e-13 * (np.abs(Es) + np.abs(Fs)))
+        Eref = Einf + (Es - Einf) * (c * dt * k0) ** K
+        assert np.max(np.abs(E / Eref - 1)) < 1e-13
+
+
 def test_explicit_properties():
     dirs, w, Istar, ka, k0, eta = _random_collision_inputs(50, kmax=0)
     dt = 0.3
