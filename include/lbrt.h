@@ -185,7 +185,9 @@ void lbrt_destroy(lbrt_ctx *ctx);
 /*
  * nsteps >= 0 stream-collide steps.  Step k reads I_a (k even) or I_b
  * (k odd) and writes the other buffer (ping-pong; in-place is rejected):
- * the result is in I_b when nsteps is odd, in I_a otherwise.
+ * the result is in I_b when nsteps is odd, in I_a otherwise.  With
+ * nsteps = 0 the state is left as it is, E and F (if given) get the
+ * moments of I_a and diag (if given) is zeroed.
  *   kappa_a, kappa_s, eta  required (device float32, ncell each);
  *   vel      device float32 3 x ncell, required iff moving_fluid;
  *   inflow   host array of ninflow planes (ninflow <= LBRT_MAX_INFLOW), or

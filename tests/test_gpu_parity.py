@@ -150,6 +150,54 @@ def test_z_face_inflow_fp32(bc):
     assert np.max(np.abs(d[1:7] - out)) < 1e-6 * scale
 
 
+@pytest.mark.parametrize("storage,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+@pytest.mark.parametrize("shape,bc,planes", [
+    ((2, 2, 2), (wl.BC_PERIODIC,) * 6, 0),
+    ((2, 2, 2), (wl.BC_OUTFLOW,) * 6, 0),
+    ((2, 3, 2), (wl.BC_INFLOW, wl.BC_OUTFLOW, wl.BC_PERIODIC, wl.BC_PERIODIC, wl.BC_INFLOW,
+                 wl.BC_OUTFLOW), 4),
+    ((3, 2, 67), (wl.BC_OUTFLOW, wl.BC_OUTFLOW, wl.BC_INFLOW, wl.BC_INFLOW, wl.BC_PERIODIC,
+                  wl.BC_PERIODIC), 3),
+])
+def test_smallest_boxes(shape, bc, planes, storage, tol):
+    """Boxes at the smallest edge the library takes (2 cells): every tile is
+    ragged and every tap is next to a face, so a periodic wrap lands on the
+    cell's own row and every x-shifted tap of a vacuum face is a ghost.
+    Populations, E, F and the face fluxes against the oracle.  F sums
+    populations of size E with both signs, and on these boxes it nearly
+    cancels (a periodic 2^3 box relaxes to isotropy), so its rounding is
+    bounded relative to max E rather than to F's own norm."""
+    st = {"fp64": L().LBRT_FP64, "fp32": L().LBRT_FP32}[storage]
+    p = wl.random_problem(61, shape=shape, npoints=50, bc=bc, inflow_planes=planes, steps=3)
+    print(f"smallest box {shape} {storage}", flush=True)
+    res = gh.run_problem(p, storage=st)
+    I, E, F, fluxes = oracle_run(p, res["I0_eff"], p.steps)
+    eI, mI, mE = gh.rel_l2(res["I"], I), max_rel(res["I"], I), max_rel(res["E"], E)
+    dF = float(np.max(np.abs(res["F"] - F)) / np.max(np.abs(E)))
+    print(f"I rel L2 {eI:.3e} max/max {mI:.3e}; E max/max {mE:.3e}; "
+          f"max |dF| / max E {dF:.3e}", flush=True)
+    assert eI < tol and mI < tol and mE < tol and dF < tol
+    d = res["diag"]
+    scale = res["I0_eff"].sum()
+    ftol = 1e-12 if storage == "fp64" else 1e-6
+    assert np.max(np.abs(d[1:7] - sum(f[0] for f in fluxes))) < ftol * scale
+    assert abs(d[7] - sum(f[1] for f in fluxes)) < ftol * scale
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp32"])
+def test_zero_steps_gives_the_moments_of_the_input(storage):
+    """nsteps = 0 leaves the state untouched and writes E and F of I_a."""
+    st = {"fp64": L().LBRT_FP64, "fp32": L().LBRT_FP32}[storage]
+    p = wl.random_problem(63, shape=(5, 7, 70), npoints=26, steps=0)
+    res = gh.run_problem(p, storage=st)
+    assert np.array_equal(res["I"], res["I0_eff"].reshape(res["I"].shape))
+    E, F = orc.moments(res["I0_eff"], p.dirs)
+    tol = 1e-13 if storage == "fp64" else 1e-6
+    assert max_rel(res["E"], E) < tol
+    assert max(max_rel(res["F"][a], F[a]) for a in range(3)) < tol
+    assert np.all(res["diag"] == 0.0)
+
+
 def test_step_with_inflow_graph_replays_match_eager():
     """lbrt_step with inflow planes enqueues kernels only (its ghost table is
     written by a kernel), so it can be captured: replays of the captured
