@@ -184,6 +184,30 @@ def test_smallest_boxes(shape, bc, planes, storage, tol):
     assert abs(d[7] - sum(f[1] for f in fluxes)) < ftol * scale
 
 
+@pytest.mark.parametrize("storage", ["bf16", "fp16", "bf16s", "fp16s"])
+@pytest.mark.parametrize("shape,bc,planes", [
+    ((2, 2, 2), (wl.BC_PERIODIC,) * 6, 0),
+    ((2, 3, 2), (wl.BC_INFLOW, wl.BC_OUTFLOW, wl.BC_PERIODIC, wl.BC_PERIODIC, wl.BC_INFLOW,
+                 wl.BC_OUTFLOW), 4),
+])
+def test_smallest_boxes_16bit(shape, bc, planes, storage):
+    """The 16-bit storage forms (plain and equilibrium-shifted) on the
+    smallest boxes: E and F element by element within 2 k u max E after k
+    steps (the module doc's bound)."""
+    st = {"bf16": L().LBRT_BF16, "fp16": L().LBRT_FP16, "bf16s": L().LBRT_BF16_SHIFTED,
+          "fp16s": L().LBRT_FP16_SHIFTED}[storage]
+    u = 2.0 ** -8 if storage.startswith("bf16") else 2.0 ** -11
+    p = wl.random_problem(61, shape=shape, npoints=50, bc=bc, inflow_planes=planes, steps=3)
+    print(f"smallest box {shape} {storage}", flush=True)
+    res = gh.run_problem(p, storage=st)
+    _, E, F, _ = oracle_run(p, res["I0_eff"], p.steps)
+    bound = 2.0 * p.steps * u * np.max(np.abs(E))
+    dE = float(np.max(np.abs(res["E"] - E)))
+    dF = float(np.max(np.abs(res["F"] - F)))
+    print(f"|dE| {dE:.3e} |dF| {dF:.3e} bound {bound:.3e}", flush=True)
+    assert dE <= bound and dF <= bound
+
+
 @pytest.mark.parametrize("storage", ["fp64", "fp32"])
 def test_zero_steps_gives_the_moments_of_the_input(storage):
     """nsteps = 0 leaves the state untouched and writes E and F of I_a."""
