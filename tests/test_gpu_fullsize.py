@@ -358,3 +358,43 @@ def test_moving_192_fp64_adjoint_per_cell_finite_differences():
                   f"err/bound {abs(fd - ad) / bound:.2f}", flush=True)
     ctx64.close()
     assert worst < 1.0
+
+
+def test_largest_grid_exact_shift():
+    """The largest grid the library takes (1023 x 1024 x 2048 cells, just
+    under 2^31; 12.9e9 populations per state with the six axis directions),
+    periodic faces, dt = dx and no medium: one step moves every population
+    by exactly one cell along its axis (Sec. 4.1.1), bit for bit, and the
+    FP64 energy sum is the input's.  The direction planes then lie up to
+    48 GB apart, past every 32-bit element or byte offset."""
+    torch = gh.torch_mod()
+    L = gh.lib()
+    nz, ny, nx = 1023, 1024, 2048
+    dirs, w = wl.lebedev(6)
+    desc = L.Desc(nx=nx, ny=ny, nz=nz, dt=1.0, dirs=dirs, weights=w,
+                  bc=(L.LBRT_BC_PERIODIC,) * 6)
+    n = desc.ncell
+    assert n < 2 ** 31 and 6 * n > 2 ** 33
+    print(f"largest grid {nz}x{ny}x{nx} x 6, {n} cells", flush=True)
+    ctx = L.lbrt_init(desc)
+    g = torch.Generator(device="cuda").manual_seed(71)
+    Ia = torch.rand(6 * n, generator=g, device="cuda")
+    Ib = torch.empty_like(Ia)
+    zero = torch.zeros(n, device="cuda")
+    diag = torch.zeros(L.LBRT_DIAG_LEN, dtype=torch.float64, device="cuda")
+    L.lbrt_step(ctx, Ia, Ib, zero, zero, zero, nsteps=1, diag=diag)
+    torch.cuda.synchronize()
+    E0 = 0.0
+    for i in range(6):
+        a = int(np.argmax(np.abs(dirs[i])))
+        src = Ia[i * n:(i + 1) * n].view(nz, ny, nx)
+        ref = torch.roll(src, int(np.sign(dirs[i][a])), dims=2 - a)
+        assert torch.equal(Ib[i * n:(i + 1) * n].view(nz, ny, nx), ref), i
+        del ref
+        E0 += float(torch.sum(src, dtype=torch.float64))
+    d = diag.cpu().numpy()
+    print(f"sum E {d[0]:.12e} vs input {E0:.12e}", flush=True)
+    # per-cell E is an FP32 sum of six values, the total an FP64 sum
+    assert abs(d[0] - E0) < 1e-6 * E0
+    assert np.all(d[1:8] == 0.0)
+    ctx.close()
