@@ -398,3 +398,6 @@ def test_largest_grid_exact_shift():
     assert abs(d[0] - E0) < 1e-6 * E0
     assert np.all(d[1:8] == 0.0)
     ctx.close()
+    # hand the ~120 GB back to the device for the tests that follow
+    del Ia, Ib, zero, src
+    torch.cuda.empty_cache()
