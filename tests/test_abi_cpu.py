@@ -104,3 +104,42 @@ def test_state_bytes():
         assert L.state_bytes(st, 50, 33) == off + 4 * 33
     assert L.state_e_offset(L.LBRT_FP32, 50, 33) == 0
     assert L.library().lbrt_state_bytes(9, 50, 33) == -1
+
+
+def test_validate_survives_malformed_statements():
+    """Seeded malformed problem statements (bad sizes, NaN or negative
+    dt/dx, broken or empty rules, unknown boundary, storage, collision and
+    rounding codes) are each answered with one of the documented status
+    codes and a message, never a crash; a good statement still passes after
+    them."""
+    import random
+    L = _lib()
+    rng = random.Random(5)
+    rules = [wl.lebedev(k) for k in (6, 26, 110, 194)]
+    codes = {L.LBRT_OK, L.LBRT_E_INVAL, L.LBRT_E_CFL, L.LBRT_E_QUAD, L.LBRT_E_UNSUPPORTED}
+    for it in range(3000):
+        dirs, w = (a.copy() for a in rules[rng.randrange(len(rules))])
+        m = rng.random()
+        if m < 0.1 and len(w) > 1:
+            dirs, w = dirs[:-1], w[:-1]
+        elif m < 0.2:
+            dirs[rng.randrange(len(w))] *= rng.choice([0.0, 2.0, float("nan"), -1.0])
+        elif m < 0.3:
+            w[rng.randrange(len(w))] = rng.choice([-1.0, 0.0, float("inf"), float("nan")])
+        elif m < 0.35:
+            dirs, w = np.zeros((0, 3)), np.zeros(0)
+        dims = [rng.choice([-5, 0, 1, 2, 3, 17, 64, 2048, 1 << 16, 1 << 30]) for _ in range(3)]
+        d = L.Desc(nx=dims[0], ny=dims[1], nz=dims[2],
+                   dt=rng.choice([0.5, 1.0, 1.5, 0.0, -1.0, float("nan")]), dirs=dirs, weights=w,
+                   bc=[rng.choice([0, 1, 2, -1, 3, 99]) for _ in range(6)],
+                   dx=rng.choice([1.0, 0.0, -2.0, float("inf")]),
+                   storage=rng.choice([0, 1, 2, 3, 4, 5, 6, -1, 77]),
+                   collision=rng.choice([0, 1, 2, 3, -2]),
+                   lambda_iters=rng.choice([-1, 0, 1, 5, 1000]),
+                   lam=rng.choice([0.0, 0.5, 3.0, -3.0, float("nan")]),
+                   moving_fluid=rng.random() < 0.3, rounding=rng.choice([0, 1, 2, -1]))
+        rc = L.lbrt_validate(d)
+        assert rc in codes, (it, rc)
+        if rc != L.LBRT_OK:
+            assert L.lbrt_last_error()
+    assert L.lbrt_validate(_desc()) == L.LBRT_OK
